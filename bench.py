@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput of the flow -> RoI-mask hot path on one MI355X.
+
+Workload (headline): the plain per-pair path over one stream of 64
+consecutive 2048x2048 uint16 frames (12-bit moving-cell synthetic frames:
+background 1200, noise sigma 25, 200 Gaussian-blob cells, sigma 5-10 px,
+90 % on random walks with step sigma 1.5 px; seed 100), one roi_mask call
+per consecutive pair with the default parameters (3 levels, 15x15 window,
+3 iterations, poly_n 5 / sigma 1.1, |d| > 1 px, 5x5 square dilation).
+A step is one pass over the 63 pairs; `value` is pairs (= output frames)
+per second with every frame already resident in HBM.
+
+Beside it the JSON line carries the streaming path (previous frame's
+expansion kept resident), the batched path (16 lens streams of uneven
+sizes in one graph launch, FP32 and FP16 storage), per-pair latency
+percentiles, the roofline of the dominant kernel (the iteration kernel,
+timed with HIP events on its own stream inside the timed region) and the
+FP64 oracle timed on the host on one 2048x2048 pair.
+
+Progress goes to stderr; stdout gets exactly one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+H = W = 2048
+N_FRAMES = 64
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=N_FRAMES)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="headline path only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the frame streams "
+              "are independent; see the sharding notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2511_14419_amd import flowroi as fl
+    from paper_2511_14419_amd import synth
+
+    dev = torch.device("cuda:0")
+    fl.lib()  # fail loudly if the HIP library is missing
+    log("generating %d frames %dx%d u16" % (args.frames, H, W))
+    t = time.time()
+    seq = synth.sequence_u16(H, W, args.frames, 200, 100)
+    log("  %.1f s" % (time.time() - t))
+    frames = [torch.from_numpy(seq[i]).to(dev) for i in range(args.frames)]
+    npairs = args.frames - 1
+    p = fl.default_params()
+    flows = [torch.empty((H, W, 2), dtype=torch.float32, device=dev) for _ in range(npairs)]
+    masks = [torch.empty((H, W), dtype=torch.uint8, device=dev) for _ in range(npairs)]
+    ws = fl.alloc_workspace(fl.workspace_size(H, W, fl.ROI_U16, p), dev)
+
+    def step():
+        for i in range(npairs):
+            fl.roi_mask(frames[i], frames[i + 1], p, flow=flows[i], mask=masks[i], ws=ws)
+
+    log("warmup %d steps" % args.warmup)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    log("timed %d steps x %d pairs" % (args.steps, npairs))
+    fl.timing_reset()
+    fl.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fl.timing_enable(False)
+    k_ms, k_n, k_px, k_bytes = fl.timing_read()
+    elapsed = t1 - t0
+    value = npairs * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    achieved = k_bytes / (k_ms * 1e-3) / 1e9
+    log("plain: %.1f pairs/s, %.2f ms/step; iteration kernel %.1f GB/s over %d launches"
+        % (value, ms_per_step, achieved, k_n))
+
+    # per-pair latency (GPU time between events around each call)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(npairs)]
+    for i in range(npairs):
+        evs[i][0].record()
+        fl.roi_mask(frames[i], frames[i + 1], p, flow=flows[i], mask=masks[i], ws=ws)
+        evs[i][1].record()
+    torch.cuda.synchronize()
+    lat = [a.elapsed_time(b) for a, b in evs]
+
+    out = {
+        "metric": "frames/s flow->RoI mask (2048x2048 u16), plain per-pair path",
+        "value": round(value, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain per-pair path: 1 stream x %d frames 2048x2048 u16 (12-bit moving-cell "
+                        "frames), one roi_mask call per consecutive pair" % args.frames,
+            "pairs_per_step": npairs, "h": H, "w": W, "input": "u16",
+            "params": p.as_dict(),
+        },
+        "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)},
+        "roofline": {
+            "kernel": "k_iter (warp + update + 15x15 window + 2x2 solve)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "launches": k_n,
+            "avg_launch_us": round(1e3 * k_ms / max(k_n, 1), 3),
+            "bytes_per_launch": round(k_bytes / max(k_n, 1)),
+        },
+    }
+
+    if not args.no_extras:
+        out["streaming"] = bench_streaming(fl, frames, p, dev, args)
+        out["batched"] = bench_batched(fl, dev, args, fp16=False)
+        out["batched_fp16"] = bench_batched(fl, dev, args, fp16=True)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(seq)
+    print(json.dumps(out), flush=True)
+
+
+def bench_streaming(fl, frames, p, dev, args):
+    import torch
+    npairs = len(frames) - 1
+    s = fl.Stream(H, W, fl.ROI_U16, p)
+    flow = torch.empty((H, W, 2), dtype=torch.float32, device=dev)
+    mask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    for _ in range(args.warmup):
+        s.reset()
+        for f in frames:
+            s.push(f, flow, mask)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 0
+    for _ in range(args.steps):
+        s.reset()
+        for f in frames:
+            if s.push(f, flow, mask) == fl.ROI_OK:
+                n += 1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s.close()
+    r = {"frames_per_s": round(n / dt, 2), "pairs": n}
+    log("streaming: %.1f frames/s" % r["frames_per_s"])
+    return r
+
+
+def bench_batched(fl, dev, args, fp16):
+    import torch
+
+    from paper_2511_14419_amd import synth
+    seqs = synth.lens_streams(16, 2)
+    prevs = [torch.from_numpy(s[0]).to(dev) for s in seqs]
+    nexts = [torch.from_numpy(s[1]).to(dev) for s in seqs]
+    flows = [torch.empty((x.shape[0], x.shape[1], 2), dtype=torch.float32, device=dev) for x in prevs]
+    masks = [torch.empty(x.shape, dtype=torch.uint8, device=dev) for x in prevs]
+    p = fl.default_params(flags=fl.ROI_FP16_STORAGE if fp16 else 0)
+    pairs = fl.make_pairs(prevs, nexts, flows, masks)
+    ws = fl.alloc_workspace(fl.batched_workspace_size(pairs, fl.ROI_U16, p), dev)
+    for _ in range(max(args.warmup, 1)):
+        fl.roi_mask_batched(pairs, fl.ROI_U16, p, ws)
+    torch.cuda.synchronize()
+    reps = max(args.steps, 5)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fl.roi_mask_batched(pairs, fl.ROI_U16, p, ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    px = sum(x.numel() for x in prevs)
+    r = {"pairs": len(prevs), "ms_per_launch": round(dt * 1e3, 3), "mpx_per_s": round(px / dt / 1e6, 1),
+         "frames_2048_equiv_per_s": round(px / dt / (H * W), 2), "storage": "f16" if fp16 else "f32"}
+    log("batched %s: %s" % (r["storage"], r))
+    return r
+
+
+def cpu_baseline(seq):
+    import numpy as np
+
+    import oracle
+    log("cpu baseline: FP64 oracle on one 2048x2048 pair")
+    a, b = seq[0].astype(np.float64), seq[1].astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.roi_mask(a, b)
+    dt = time.perf_counter() - t0
+    r = {"value": round(1.0 / dt, 4), "unit": "frames/s", "cores": oracle.num_threads(), "kind": "oracle",
+         "sample": "1 pair of the 2048x2048 u16 sequence (frames 0 -> 1), full path, %.2f s" % dt}
+    log("  %s" % r)
+    return r
+
+
+if __name__ == "__main__":
+    main()

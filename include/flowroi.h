@@ -1,0 +1,222 @@
+/*
+ * flowroi.h — C ABI of the MI355X (gfx950) FlowRoI hot path.
+ *
+ * FlowRoI (Method section, "Optical flow extraction" and "Region of Interest
+ * extraction") turns a pair of adjacent grayscale frames into a dense optical
+ * flow field with Farneback's estimator, keeps the pixels whose motion
+ * exceeds a threshold, and cleans the result with morphology into a binary
+ * RoI mask that a host-side JPEG2000 RoI encoder consumes. This library runs
+ * that path as HIP kernels; the estimator is the two-frame polynomial-
+ * expansion method (Farneback, SCIA 2003), whose constants the paper leaves
+ * open; the defaults below are the frozen reading.
+ *
+ * Conventions shared by every entry point
+ *   - Frames are row-major, h rows by w columns, `pitch` elements between
+ *     the starts of consecutive rows (pitch >= w). Element type: roi_dtype.
+ *   - x is the column, y the row. Flow is interleaved float (dx, dy) per
+ *     pixel, h*w*2 floats with row pitch w, pointing from prev to next:
+ *     next(x + d) ~ prev(x).
+ *   - The mask is h*w uint8 values in {0, 1}, row pitch w.
+ *   - Every pointer named "device" is device memory on the current HIP
+ *     device, owned by the caller; the library never frees or retains it.
+ *     Host pointers are read during the call only.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and runs asynchronously. Parameter errors are detected on the host
+ *     before anything is enqueued; on any error status nothing was enqueued
+ *     (except ROI_EDEVICE, which reports a failed launch).
+ *   - No entry point allocates device memory except roi_stream_create.
+ *     Scratch comes from a caller-provided workspace of at least
+ *     roi_workspace_size() bytes, 256-byte aligned.
+ *   - Calls that share a workspace or a stream context must not overlap.
+ */
+#ifndef FLOWROI_H
+#define FLOWROI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ROI_OK = 0,
+    ROI_PRIMED = 1,          /* stream push: first frame stored, no flow/mask yet */
+    ROI_EINVAL = -1,         /* bad pointer, size or parameter */
+    ROI_ENOMEM = -2,         /* workspace too small / device allocation failed */
+    ROI_EDEVICE = -3,        /* a HIP call or kernel launch failed */
+    ROI_EUNSUPPORTED = -4    /* valid request outside what the kernels handle */
+} roi_status;
+
+typedef enum { ROI_U8 = 0, ROI_U16 = 1, ROI_F32 = 2 } roi_dtype;
+
+enum {
+    ROI_THRESH_ABS = 0,      /* keep |d| > thresh (pixels) */
+    ROI_THRESH_TOP = 1       /* keep the top `thresh` fraction of |d| (RoI threshold, Table 1) */
+};
+
+enum {
+    ROI_SE_SQUARE = 0,       /* (2r+1)^2 square */
+    ROI_SE_DISC = 1          /* offsets with u^2 + v^2 <= r^2 */
+};
+
+enum {
+    ROI_USE_INITIAL_FLOW = 1u, /* `flow` holds an initial flow on entry (see roi_mask) */
+    ROI_FP16_STORAGE = 2u      /* pyramid images and expansions stored as FP16; FP32 math */
+};
+
+/* Parameters of the path. Farneback's constants are not given by the paper
+ * (it only names the "dense Farneback" estimator); the RoI threshold is
+ * Table 1's (the paper's example: 0.2 keeps the top 20 %). */
+typedef struct roi_params {
+    int32_t levels;        /* pyramid levels, 1..10; level l+1 = binomial-blurred level l at even pixels */
+    int32_t winsize;       /* side of the square pooling window, odd, 1..15 */
+    int32_t iterations;    /* displacement updates per level, 1..64 */
+    int32_t poly_n;        /* expansion neighbourhood side, 5 or 7 */
+    float poly_sigma;      /* Gaussian applicability sigma (pixels), > 0 */
+    float eps;             /* regulariser: den = max(det G, eps (tr G)^2), > 0 */
+    int32_t thresh_mode;   /* ROI_THRESH_ABS or ROI_THRESH_TOP */
+    float thresh;          /* ABS: pixels, >= 0; TOP: fraction in (0, 1) */
+    int32_t dilate_radius; /* structuring-element radius, 0..32 */
+    int32_t se_shape;      /* ROI_SE_SQUARE or ROI_SE_DISC */
+    uint32_t flags;        /* ROI_USE_INITIAL_FLOW | ROI_FP16_STORAGE */
+} roi_params;
+
+/* Defaults: levels 3, winsize 15, iterations 3, poly_n 5, poly_sigma 1.1,
+ * eps 1e-3, ABS threshold 1.0 px, square dilation of radius 2, no flags. */
+void roi_default_params(roi_params *p);
+
+/* Host-only check of a request (no device work). ROI_OK, ROI_EINVAL for a
+ * bad value, ROI_EUNSUPPORTED for valid values the kernels do not handle.
+ * h or w equal to 0 is valid (empty frame: every call is a no-op). */
+roi_status roi_validate(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p);
+
+/* Workspace bytes roi_mask needs for this request (0 if roi_validate fails). */
+size_t roi_workspace_size(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p);
+
+/* The hot path for one frame pair: flow prev -> next, the magnitude
+ * threshold, and the dilation into the RoI mask.
+ *   prev, next  device, h x w frames of `dtype`, row pitch `pitch` elements.
+ *   flow        device, h*w*2 floats, output. With ROI_USE_INITIAL_FLOW it
+ *               is also read first: the coarsest level L-1 starts from
+ *               flow(min(2^(L-1) y, h-1), min(2^(L-1) x, w-1)) / 2^(L-1).
+ *   mask        device, h*w uint8, output: 1 inside the RoI, 0 elsewhere.
+ *               May be NULL to skip threshold and dilation.
+ *   ws          device workspace of ws_bytes >= roi_workspace_size(...).
+ * Returns ROI_OK once the work is enqueued. */
+roi_status roi_mask(const void *prev, const void *next, int32_t h, int32_t w, int64_t pitch,
+                    roi_dtype dtype, const roi_params *p, float *flow, uint8_t *mask, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* Squared threshold tau^2 that the last roi_mask / roi_mask_batched call on
+ * this workspace applied (ABS: thresh^2; TOP: the (k+1)-th largest |d|^2
+ * with k = floor(q h w)), copied to the host after synchronising `stream`.
+ * For a batched call, `index` selects the pair. */
+roi_status roi_read_tau2(const void *ws, int32_t index, float *tau2_out, void *stream);
+
+/* ---- Single steps, for testing each step in isolation ------------------ */
+
+/* One pyramid step (step a2): dst(i, j) = sum_{u,v} k(u) k(v) src(2i+u, 2j+v),
+ * k = [1 4 6 4 1]/16, replicate border. src device h x w floats (pitch w),
+ * dst device ceil(h/2) x ceil(w/2) floats (pitch ceil(w/2)). */
+roi_status roi_pyr_down(const float *src, int32_t h, int32_t w, float *dst, void *stream);
+
+/* Polynomial expansion (step a3) of one frame: weighted least-squares fit
+ * of f ~ x^T A x + b^T x + c over the poly_n x poly_n neighbourhood with
+ * Gaussian applicability (poly_sigma), replicate border. Output `coef` is
+ * device 5 x h x w floats (plane stride h*w): b_x, b_y, A_xx, A_yy, A_xy
+ * (A_xy is the off-diagonal entry, half the x*y coefficient). Uses
+ * p->poly_n, p->poly_sigma and p->flags & ROI_FP16_STORAGE (rounds the
+ * stored values to FP16 precision). */
+roi_status roi_poly_expand(const void *img, int32_t h, int32_t w, int64_t pitch, roi_dtype dtype,
+                           const roi_params *p, float *coef, void *stream);
+
+/* ---- Batched: several pairs of uneven sizes in one captured launch ------ */
+
+typedef struct roi_pair {
+    const void *prev;      /* device frame */
+    const void *next;      /* device frame */
+    float *flow;           /* device h*w*2 floats */
+    uint8_t *mask;         /* device h*w uint8 (must not be NULL) */
+    int32_t h, w;
+    int64_t pitch;         /* elements */
+} roi_pair;
+
+/* Workspace for roi_mask_batched over these pairs (0 on invalid input). */
+size_t roi_batched_workspace_size(int32_t n, const roi_pair *pairs, roi_dtype dtype, const roi_params *p);
+
+/* All n pairs through the whole path. Each pair's result is the one roi_mask
+ * gives for it alone (the same kernels, the same per-pixel arithmetic).
+ * The launch sequence for a given (pairs, dtype, params, ws) is captured
+ * into a HIP graph on first use and replayed afterwards. n in 1..256. */
+roi_status roi_mask_batched(int32_t n, const roi_pair *pairs, roi_dtype dtype, const roi_params *p,
+                            void *ws, size_t ws_bytes, void *stream);
+
+/* ---- Streaming: one context per camera stream --------------------------- */
+
+/* Allocates the resident state of one stream (the previous frame's pyramid
+ * expansions and the flow/mask scratch) on the current device. */
+roi_status roi_stream_create(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p, void **out_ctx);
+
+/* Pushes the next frame. The first push after create (or reset) stores the
+ * frame and returns ROI_PRIMED without writing flow/mask. Later pushes write
+ * the flow from the previous frame to this one and its mask, exactly as
+ * roi_mask(previous, frame) would, and return ROI_OK. */
+roi_status roi_stream_push(void *ctx, const void *frame, int64_t pitch, float *flow, uint8_t *mask,
+                           void *stream);
+
+/* Forget the stored frame: the next push primes again. */
+roi_status roi_stream_reset(void *ctx);
+
+/* Resident device bytes of a stream context with these settings. */
+size_t roi_stream_state_bytes(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p);
+
+void roi_stream_destroy(void *ctx);
+
+/* Several stream contexts advanced together: frames[i] is pushed into
+ * ctxs[i], all in one batched launch sequence on `stream`. status[i] gets
+ * ROI_PRIMED or ROI_OK per context. Contexts must share dtype and params.
+ * n in 1..256. */
+roi_status roi_stream_push_many(int32_t n, void *const *ctxs, const void *const *frames,
+                                const int64_t *pitches, float *const *flows, uint8_t *const *masks,
+                                int32_t *status, void *stream);
+
+/* ---- Kernel timing ------------------------------------------------------ */
+
+/* When enabled, the library records HIP events around every launch of the
+ * iteration kernel (warp + update + window + solve, the dominant kernel) on
+ * the stream it is launched on. roi_timing_read synchronises those events
+ * and returns, summed since the last reset: kernel time (ms), launches,
+ * output pixels, and algorithmic bytes (expansion planes of both frames at
+ * the storage width + prior flow read + flow written + |d|^2 written, each
+ * counted once per output pixel). Launches captured into graphs are not
+ * timed. */
+void roi_timing_enable(int32_t on);
+roi_status roi_timing_read(double *total_ms, int64_t *launches, int64_t *pixels, double *bytes);
+void roi_timing_reset(void);
+
+/* ---- Tuning -------------------------------------------------------------- */
+
+/* The iteration kernel walks strips of 64 columns; the strip height only
+ * changes how the work is split, never the result (bitwise). mode 1
+ * (default): the first uncaptured launch for a new (level size, window,
+ * storage) times the candidate heights {8, 16, ..., 256} on the real data
+ * and keeps the fastest; mode 0: a size heuristic; mode 2: like 1 after
+ * forgetting every tuned entry. */
+void roi_autotune(int32_t mode);
+
+/* Force every iteration launch to one strip height (a multiple of 8), or 0
+ * to return to tuned/heuristic heights. ROI_EINVAL for other values. */
+roi_status roi_set_strip(int32_t strip);
+
+/* Tuned strip height for a level of h x w with this window and storage
+ * (fp16 != 0: FP16), or 0 if that shape has not been tuned yet. */
+int32_t roi_tuned_strip(int32_t h, int32_t w, int32_t winsize, int32_t fp16);
+
+const char *roi_status_str(roi_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLOWROI_H */

@@ -1,0 +1,980 @@
+// Host side of libflowroi: C ABI (include/flowroi.h), workspace planning and
+// the launch sequence of the hot path on the caller's HIP stream.
+//
+// Sequence for one frame pair (FlowRoI Method: flow between adjacent frames,
+// then thresholding and morphology; estimator: Farneback's two-frame
+// polynomial expansion):
+//   pyramid (both frames per launch) -> expansion per level (both frames per
+//   launch) -> coarse-to-fine iterations (one launch each; the first launch
+//   of every finer level upsamples the coarser flow on the fly, the last one
+//   at full resolution also writes |d|^2) -> [top-q radix select] ->
+//   threshold + dilation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "flowroi.h"
+#include "kernels.h"
+
+using namespace flowroi;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int MAX_LEVELS = 10;
+constexpr int MAX_BATCH = 256;
+constexpr size_t HDR_BYTES = sizeof(SelState) * MAX_BATCH; // per-pair threshold state slots
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int level_dim(int n, int l)
+{
+    for (int k = 0; k < l; ++k) n = (n + 1) / 2;
+    return n;
+}
+
+float dc_of(roi_dtype d) { return d == ROI_U8 ? 128.0f : (d == ROI_U16 ? 2048.0f : 0.0f); }
+
+size_t dtype_bytes(roi_dtype d) { return d == ROI_U8 ? 1 : (d == ROI_U16 ? 2 : 4); }
+
+// Device buffers of one frame pair, as byte offsets from the pair's base.
+struct Level {
+    int h, w, pitch;  // pitch in elements, a multiple of 64
+    size_t img[2];    // pyramid image of each frame (levels >= 1)
+    size_t r[2];      // 5-plane expansion of each frame
+    size_t fa, fb;    // flow ping-pong (fb unused at level 0: the caller's buffer)
+};
+
+struct Plan {
+    int L;
+    bool fp16;
+    size_t ts;        // storage bytes per expansion value
+    size_t is;        // storage bytes per pyramid image value (FP64, or FP16)
+    Level lv[MAX_LEVELS];
+    size_t init_off;  // coarsest-level initial flow
+    size_t m2_off;    // |d|^2 at full resolution, pitch lv[0].pitch
+    size_t hist_off;  // radix-select histogram
+    size_t bytes;
+};
+
+Plan make_plan(int h, int w, const roi_params *p)
+{
+    Plan pl{};
+    pl.L = p->levels;
+    pl.fp16 = (p->flags & ROI_FP16_STORAGE) != 0;
+    pl.ts = pl.fp16 ? 2 : 4;
+    pl.is = pl.fp16 ? 2 : 8;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, ALIGN);
+        return o;
+    };
+    for (int l = 0; l < pl.L; ++l) {
+        Level &v = pl.lv[l];
+        v.h = level_dim(h, l);
+        v.w = level_dim(w, l);
+        v.pitch = (int)align_up((size_t)v.w, 64);
+        const size_t plane = (size_t)v.h * v.pitch;
+        for (int f = 0; f < 2; ++f) {
+            v.img[f] = l > 0 ? take(plane * pl.is) : 0;
+            v.r[f] = take(5 * plane * pl.ts);
+        }
+        v.fa = take(plane * sizeof(float2));
+        v.fb = l > 0 ? take(plane * sizeof(float2)) : 0;
+    }
+    const Level &c = pl.lv[pl.L - 1];
+    pl.init_off = take((size_t)c.h * c.pitch * sizeof(float2));
+    pl.m2_off = take((size_t)pl.lv[0].h * pl.lv[0].pitch * sizeof(float));
+    pl.hist_off = take(SEL_BINS * sizeof(uint32_t));
+    pl.bytes = off;
+    return pl;
+}
+
+// ---------------------------------------------------------------- kernel timing
+
+struct TimedLaunch {
+    hipEvent_t e0, e1;
+    int64_t px;
+    double bytes;
+};
+
+struct Timing {
+    std::mutex mu;
+    bool on = false;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> pool;
+    double done_ms = 0, done_bytes = 0;
+    int64_t done_n = 0, done_px = 0;
+
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+    }
+} g_timing;
+
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+    return cs != hipStreamCaptureStatusNone;
+}
+
+// ---------------------------------------------------------------- launch helpers
+
+#define LAUNCH_CHECK()                                                                                  \
+    do {                                                                                                \
+        if (hipGetLastError() != hipSuccess) return ROI_EDEVICE;                                        \
+    } while (0)
+
+struct PolyConsts {
+    int n;
+    double kv0[7], kv1[7], kv2[7], hx[7], hy[7], hxy[7], hxx[7], hyy[7];
+};
+
+// Separable form of the weighted least-squares quadratic fit with Gaussian
+// applicability a(t) = exp(-t^2 / (2 sigma^2)) on t = -n..n. With moments
+// m0 = sum a, m2 = sum a t^2, m4 = sum a t^4 the normal equations decouple:
+//   b_x = <x, f> / (m0 m2), b_y = <y, f> / (m0 m2), c_xy = <xy, f> / m2^2,
+//   c_xx = <x^2 - m2/m0, f> / (m0 m4 - m2^2) (and c_yy likewise),
+// every inner product being a separable correlation of f.
+PolyConsts poly_consts(int poly_n, double sigma)
+{
+    PolyConsts c{};
+    const int n = poly_n / 2;
+    c.n = n;
+    double a[7], m0 = 0, m2 = 0, m4 = 0;
+    for (int t = -n; t <= n; ++t) {
+        a[t + n] = std::exp(-(double)(t * t) / (2 * sigma * sigma));
+        m0 += a[t + n];
+        m2 += a[t + n] * t * t;
+        m4 += a[t + n] * t * t * t * t;
+    }
+    const double r = m2 / m0, dxx = m0 * m4 - m2 * m2;
+    for (int t = -n; t <= n; ++t) {
+        const double at = a[t + n];
+        c.kv0[t + n] = at;
+        c.kv1[t + n] = (t * at);
+        c.kv2[t + n] = ((t * t - r) * at);
+        c.hx[t + n] = (t * at / (m0 * m2));
+        c.hy[t + n] = (at / (m0 * m2));
+        c.hxy[t + n] = (t * at / (2 * m2 * m2));
+        c.hxx[t + n] = ((t * t - r) * at / dxx);
+        c.hyy[t + n] = (at / dxx);
+    }
+    return c;
+}
+
+void fill_poly(PolyArgs &pa, const PolyConsts &c)
+{
+    pa.n = c.n;
+    std::memcpy(pa.kv0, c.kv0, sizeof c.kv0);
+    std::memcpy(pa.kv1, c.kv1, sizeof c.kv1);
+    std::memcpy(pa.kv2, c.kv2, sizeof c.kv2);
+    std::memcpy(pa.hx, c.hx, sizeof c.hx);
+    std::memcpy(pa.hy, c.hy, sizeof c.hy);
+    std::memcpy(pa.hxy, c.hxy, sizeof c.hxy);
+    std::memcpy(pa.hxx, c.hxx, sizeof c.hxx);
+    std::memcpy(pa.hyy, c.hyy, sizeof c.hyy);
+}
+
+template <typename TIn, typename TOut>
+void launch_pyr(const PyrArgs &a, int frames, hipStream_t s)
+{
+    dim3 g((a.w2 + PYR_TW - 1) / PYR_TW, (a.h2 + PYR_TH - 1) / PYR_TH, frames);
+    hipLaunchKernelGGL((k_pyr_down<TIn, TOut>), g, dim3(256), 0, s, a);
+}
+
+template <typename TIn, typename TOut>
+void launch_poly(const PolyArgs &a, int frames, hipStream_t s)
+{
+    dim3 g((a.w + PE_TW - 1) / PE_TW, (a.h + PE_TH - 1) / PE_TH, frames);
+    hipLaunchKernelGGL((k_polyexp<TIn, TOut>), g, dim3(256), 0, s, a);
+}
+
+template <typename TOut>
+void launch_pyr_raw(roi_dtype dt, const PyrArgs &a, int frames, hipStream_t s)
+{
+    if (dt == ROI_U8) launch_pyr<uint8_t, TOut>(a, frames, s);
+    else if (dt == ROI_U16) launch_pyr<uint16_t, TOut>(a, frames, s);
+    else launch_pyr<float, TOut>(a, frames, s);
+}
+
+template <typename TOut>
+void launch_poly_raw(roi_dtype dt, const PolyArgs &a, int frames, hipStream_t s)
+{
+    if (dt == ROI_U8) launch_poly<uint8_t, TOut>(a, frames, s);
+    else if (dt == ROI_U16) launch_poly<uint16_t, TOut>(a, frames, s);
+    else launch_poly<float, TOut>(a, frames, s);
+}
+
+// Pyramid and expansions of `nf` (1 or 2) frames into expansion sets `set[]`.
+roi_status enqueue_expand(const Plan &pl, uint8_t *base, int nf, const void *const *frames, int64_t pitch,
+                          roi_dtype dt, const roi_params *p, const int *set, hipStream_t s)
+{
+    const PolyConsts pc = poly_consts(p->poly_n, p->poly_sigma);
+    for (int l = 1; l < pl.L; ++l) {
+        const Level &src = pl.lv[l - 1], &dst = pl.lv[l];
+        PyrArgs a{};
+        for (int f = 0; f < nf; ++f) {
+            a.src[f] = l == 1 ? frames[f] : (const void *)(base + src.img[set[f]]);
+            a.dst[f] = base + dst.img[set[f]];
+        }
+        a.src_pitch = l == 1 ? pitch : src.pitch;
+        a.dc = l == 1 ? dc_of(dt) : 0.0f;
+        a.dst_pitch = dst.pitch;
+        a.h = src.h;
+        a.w = src.w;
+        a.h2 = dst.h;
+        a.w2 = dst.w;
+        if (pl.fp16) {
+            if (l == 1) launch_pyr_raw<__half>(dt, a, nf, s);
+            else launch_pyr<__half, __half>(a, nf, s);
+        } else {
+            if (l == 1) launch_pyr_raw<double>(dt, a, nf, s);
+            else launch_pyr<double, double>(a, nf, s);
+        }
+        LAUNCH_CHECK();
+    }
+    for (int l = 0; l < pl.L; ++l) {
+        const Level &v = pl.lv[l];
+        PolyArgs a{};
+        fill_poly(a, pc);
+        for (int f = 0; f < nf; ++f) {
+            a.src[f] = l == 0 ? frames[f] : (const void *)(base + v.img[set[f]]);
+            a.dst[f] = base + v.r[set[f]];
+        }
+        a.src_pitch = l == 0 ? pitch : v.pitch;
+        a.dc = l == 0 ? dc_of(dt) : 0.0f;
+        a.dplane = (int64_t)v.h * v.pitch;
+        a.dpitch = v.pitch;
+        a.h = v.h;
+        a.w = v.w;
+        if (pl.fp16) {
+            if (l == 0) launch_poly_raw<__half>(dt, a, nf, s);
+            else launch_poly<__half, __half>(a, nf, s);
+        } else {
+            if (l == 0) launch_poly_raw<float>(dt, a, nf, s);
+            else launch_poly<double, float>(a, nf, s);
+        }
+        LAUNCH_CHECK();
+    }
+    return ROI_OK;
+}
+
+// ---------------------------------------------------------------- iteration launch + strip autotuner
+
+// The strip height of the iteration kernel only changes how work is split
+// (results are bitwise identical for every strip), so it is tuned per
+// (level size, window, storage) by timing the candidates on the real data
+// the first time a shape is seen (each candidate run rewrites the same
+// output). Captured launches and disabled tuning use the heuristic.
+constexpr int STRIP_CANDIDATES[] = {8, 16, 32, 64, 128, 256};
+
+struct TuneState {
+    std::mutex mu;
+    int mode = 1;        // 0 heuristic only, 1 tune on first use
+    int forced = 0;      // > 0: every launch uses this strip
+    std::map<std::tuple<int, int, int, int>, int> best;
+} g_tune;
+
+int heuristic_strip(int h, int w)
+{
+    // aim for >= 1024 workgroups (4 per CU) without strips shorter than 16 rows
+    const int nx = (w + IT_TW - 1) / IT_TW;
+    int strip = 256;
+    while (strip > 16 && (long)nx * ((h + strip - 1) / strip) < 1024) strip /= 2;
+    return strip;
+}
+
+template <typename TS>
+void launch_iter_t(const IterArgs &a, int strip, hipStream_t s)
+{
+    const int nx = (a.w + IT_TW - 1) / IT_TW, ny = (a.h + strip - 1) / strip;
+    const int nt = nx * ny;
+    dim3 g(nt), b(256);
+    switch (a.R) {
+    case 0: hipLaunchKernelGGL((k_iter<TS, 0>), g, b, 0, s, a, strip, nx, nt); break;
+    case 1: hipLaunchKernelGGL((k_iter<TS, 1>), g, b, 0, s, a, strip, nx, nt); break;
+    case 2: hipLaunchKernelGGL((k_iter<TS, 2>), g, b, 0, s, a, strip, nx, nt); break;
+    case 3: hipLaunchKernelGGL((k_iter<TS, 3>), g, b, 0, s, a, strip, nx, nt); break;
+    case 4: hipLaunchKernelGGL((k_iter<TS, 4>), g, b, 0, s, a, strip, nx, nt); break;
+    case 5: hipLaunchKernelGGL((k_iter<TS, 5>), g, b, 0, s, a, strip, nx, nt); break;
+    case 6: hipLaunchKernelGGL((k_iter<TS, 6>), g, b, 0, s, a, strip, nx, nt); break;
+    default: hipLaunchKernelGGL((k_iter<TS, 7>), g, b, 0, s, a, strip, nx, nt); break;
+    }
+}
+
+void launch_iter_raw(const IterArgs &a, bool fp16, int strip, hipStream_t s)
+{
+    if (fp16) launch_iter_t<__half>(a, strip, s);
+    else launch_iter_t<float>(a, strip, s);
+}
+
+// Algorithmic bytes of one iteration launch: both frames' expansion planes,
+// the prior flow (none for a zero prior, a quarter per pixel when it is the
+// upsampled coarser flow), the flow written and the optional |d|^2.
+double iter_bytes(const IterArgs &a, bool fp16)
+{
+    const double px = (double)a.h * a.w;
+    double b = px * 2 * 5 * (fp16 ? 2 : 4) + px * sizeof(float2);
+    if (a.prior == PRIOR_PLAIN) b += px * sizeof(float2);
+    if (a.prior == PRIOR_UPSAMPLE) b += (double)a.hc * a.wc * sizeof(float2);
+    if (a.m2) b += px * sizeof(float);
+    return b;
+}
+
+int choose_strip(const IterArgs &a, bool fp16, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    if (g_tune.forced > 0) return g_tune.forced;
+    const auto key = std::make_tuple(a.h, a.w, a.R, fp16 ? 1 : 0);
+    auto it = g_tune.best.find(key);
+    if (it != g_tune.best.end()) return it->second;
+    if (g_tune.mode == 0 || capturing(s)) return heuristic_strip(a.h, a.w);
+    hipEvent_t e[2 * 6];
+    int n = 0;
+    for (int k = 0; k < 12; ++k)
+        if (hipEventCreate(&e[k]) == hipSuccess) ++n;
+    int best = heuristic_strip(a.h, a.w);
+    if (n == 12) {
+        float best_ms = 1e30f;
+        for (int c = 0; c < 6; ++c) {
+            const int strip = STRIP_CANDIDATES[c];
+            launch_iter_raw(a, fp16, strip, s); // warm the caches / code object
+            hipEventRecord(e[2 * c], s);
+            launch_iter_raw(a, fp16, strip, s);
+            hipEventRecord(e[2 * c + 1], s);
+        }
+        if (hipEventSynchronize(e[11]) == hipSuccess) {
+            for (int c = 0; c < 6; ++c) {
+                float ms = 0;
+                if (hipEventElapsedTime(&ms, e[2 * c], e[2 * c + 1]) == hipSuccess && ms < best_ms) {
+                    best_ms = ms;
+                    best = STRIP_CANDIDATES[c];
+                }
+            }
+        }
+    }
+    for (int k = 0; k < n; ++k) hipEventDestroy(e[k]);
+    g_tune.best[key] = best;
+    return best;
+}
+
+roi_status launch_iter(const IterArgs &a, bool fp16, hipStream_t s)
+{
+    const int strip = choose_strip(a, fp16, s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        if (g_timing.on && !capturing(s)) {
+            e0 = g_timing.get();
+            e1 = g_timing.get();
+        }
+    }
+    const bool timed = e0 && e1;
+    if (timed) hipEventRecord(e0, s);
+    launch_iter_raw(a, fp16, strip, s);
+    const bool ok = hipGetLastError() == hipSuccess;
+    if (timed) {
+        hipEventRecord(e1, s);
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        g_timing.pending.push_back({e0, e1, (int64_t)a.h * a.w, iter_bytes(a, fp16)});
+    } else {
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        if (e0) g_timing.pool.push_back(e0);
+        if (e1) g_timing.pool.push_back(e1);
+    }
+    return ok ? ROI_OK : ROI_EDEVICE;
+}
+
+// Coarse-to-fine iterations from expansion set `s1` (prev) to `s2` (next),
+// then the threshold and dilation into `mask` (skipped when mask is NULL).
+roi_status enqueue_flow(const Plan &pl, uint8_t *base, SelState *slot, int s1, int s2, int h, int w,
+                        const roi_params *p, float *flow, uint8_t *mask, hipStream_t s)
+{
+    const bool init = (p->flags & ROI_USE_INITIAL_FLOW) != 0;
+    const int L = pl.L, n = p->iterations;
+    const Level &c = pl.lv[L - 1];
+    if (init) {
+        InitArgs a{};
+        a.src = (const float2 *)flow;
+        a.src_pitch = w;
+        a.h = h;
+        a.w = w;
+        a.dst = (float2 *)(base + pl.init_off);
+        a.dst_pitch = c.pitch;
+        a.hl = c.h;
+        a.wl = c.w;
+        a.stride = 1 << (L - 1);
+        dim3 g((c.w + 63) / 64, (c.h + 3) / 4);
+        hipLaunchKernelGGL(k_init_flow, g, dim3(256), 0, s, a);
+        LAUNCH_CHECK();
+    }
+    const float2 *coarse = nullptr;
+    int coarse_pitch = 0, hc = 0, wc = 0;
+    for (int l = L - 1; l >= 0; --l) {
+        const Level &v = pl.lv[l];
+        float2 *X = (float2 *)(base + v.fa);
+        float2 *Y = l == 0 ? (float2 *)flow : (float2 *)(base + v.fb);
+        const int xp = v.pitch, yp = l == 0 ? w : v.pitch;
+        const float2 *prev_out = nullptr;
+        int prev_pitch = 0;
+        for (int it = 0; it < n; ++it) {
+            IterArgs a{};
+            a.r1 = base + v.r[s1];
+            a.r2 = base + v.r[s2];
+            a.rplane = (int64_t)v.h * v.pitch;
+            a.rpitch = v.pitch;
+            a.h = v.h;
+            a.w = v.w;
+            if (it > 0) {
+                a.prior = PRIOR_PLAIN;
+                a.fin = prev_out;
+                a.fin_pitch = prev_pitch;
+            } else if (l < L - 1) {
+                a.prior = PRIOR_UPSAMPLE;
+                a.fin = coarse;
+                a.fin_pitch = coarse_pitch;
+                a.hc = hc;
+                a.wc = wc;
+            } else if (init) {
+                a.prior = PRIOR_PLAIN;
+                a.fin = (const float2 *)(base + pl.init_off);
+                a.fin_pitch = c.pitch;
+            } else {
+                a.prior = PRIOR_ZERO;
+            }
+            const bool toY = ((n - 1 - it) % 2) == 0;
+            a.fout = toY ? Y : X;
+            a.fout_pitch = toY ? yp : xp;
+            a.R = p->winsize / 2;
+            a.eps = p->eps;
+            if (l == 0 && it == n - 1 && mask) {
+                a.m2 = (float *)(base + pl.m2_off);
+                a.m2_pitch = pl.lv[0].pitch;
+            }
+            roi_status st = launch_iter(a, pl.fp16, s);
+            if (st != ROI_OK) return st;
+            prev_out = a.fout;
+            prev_pitch = a.fout_pitch;
+        }
+        coarse = prev_out;
+        coarse_pitch = prev_pitch;
+        hc = v.h;
+        wc = v.w;
+    }
+    if (!mask) return ROI_OK;
+    const float *m2 = (const float *)(base + pl.m2_off);
+    uint32_t *hist = (uint32_t *)(base + pl.hist_off);
+    const size_t N = (size_t)h * w;
+    if (p->thresh_mode == ROI_THRESH_ABS) {
+        const float t2 = p->thresh * p->thresh;
+        uint32_t bits;
+        std::memcpy(&bits, &t2, 4);
+        hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, slot, hist, 0u, bits);
+        LAUNCH_CHECK();
+    } else {
+        const uint32_t rank = (uint32_t)std::floor((double)p->thresh * (double)N);
+        hipLaunchKernelGGL(k_sel_init, dim3(8), dim3(256), 0, s, slot, hist, rank, 0u);
+        LAUNCH_CHECK();
+        const int blocks = (int)std::min<size_t>((N + 255) / 256, 1024);
+        for (int pass = 0; pass < 3; ++pass) {
+            hipLaunchKernelGGL(k_sel_hist, dim3(blocks), dim3(256), 0, s, m2, pl.lv[0].pitch, h, w,
+                               (const SelState *)slot, hist, pass);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, slot, hist, pass);
+            LAUNCH_CHECK();
+        }
+    }
+    DilArgs d{};
+    d.m2 = m2;
+    d.m2_pitch = pl.lv[0].pitch;
+    d.st = slot;
+    d.mask = mask;
+    d.mask_pitch = w;
+    d.h = h;
+    d.w = w;
+    d.r = p->dilate_radius;
+    for (int u = -d.r; u <= d.r; ++u) {
+        int hw = d.r;
+        if (p->se_shape == ROI_SE_DISC) {
+            hw = 0;
+            while ((hw + 1) * (hw + 1) + u * u <= d.r * d.r) ++hw;
+        }
+        d.hw[u + d.r] = (int8_t)hw;
+    }
+    dim3 g((w + DIL_TW - 1) / DIL_TW, (h + DIL_TH - 1) / DIL_TH);
+    hipLaunchKernelGGL(k_dilate, g, dim3(256), 0, s, d);
+    LAUNCH_CHECK();
+    return ROI_OK;
+}
+
+bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
+
+// ---------------------------------------------------------------- graphs for batched calls
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    uint64_t tick = 0;
+};
+
+std::mutex g_graph_mu;
+std::map<std::string, GraphEntry> g_graphs;
+uint64_t g_tick = 0;
+constexpr size_t MAX_GRAPHS = 32;
+
+struct DeviceStreams {
+    hipStream_t cap = nullptr;
+    std::vector<hipStream_t> aux;
+    std::vector<hipEvent_t> ev;
+};
+std::map<int, DeviceStreams> g_dev_streams;
+
+DeviceStreams *device_streams(int naux)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    DeviceStreams &ds = g_dev_streams[dev];
+    if (!ds.cap && hipStreamCreateWithFlags(&ds.cap, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    while ((int)ds.aux.size() < naux) {
+        hipStream_t a;
+        if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        ds.aux.push_back(a);
+    }
+    while ((int)ds.ev.size() < naux + 1) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        ds.ev.push_back(e);
+    }
+    return &ds;
+}
+
+} // namespace
+
+// ================================================================= C ABI
+
+extern "C" {
+
+void roi_default_params(roi_params *p)
+{
+    if (!p) return;
+    p->levels = 3;
+    p->winsize = 15;
+    p->iterations = 3;
+    p->poly_n = 5;
+    p->poly_sigma = 1.1f;
+    p->eps = 1e-3f;
+    p->thresh_mode = ROI_THRESH_ABS;
+    p->thresh = 1.0f;
+    p->dilate_radius = 2;
+    p->se_shape = ROI_SE_SQUARE;
+    p->flags = 0;
+}
+
+roi_status roi_validate(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p)
+{
+    if (!p || h < 0 || w < 0) return ROI_EINVAL;
+    if (dtype != ROI_U8 && dtype != ROI_U16 && dtype != ROI_F32) return ROI_EINVAL;
+    if (p->levels < 1 || p->levels > MAX_LEVELS) return ROI_EINVAL;
+    if (p->winsize < 1 || p->winsize % 2 == 0) return ROI_EINVAL;
+    if (p->iterations < 1 || p->iterations > 64) return ROI_EINVAL;
+    if (p->poly_n != 3 && p->poly_n != 5 && p->poly_n != 7) return ROI_EINVAL;
+    if (!finite_pos(p->poly_sigma) || !finite_pos(p->eps)) return ROI_EINVAL;
+    if (p->thresh_mode == ROI_THRESH_ABS) {
+        if (!std::isfinite(p->thresh) || p->thresh < 0.0f) return ROI_EINVAL;
+    } else if (p->thresh_mode == ROI_THRESH_TOP) {
+        if (!(p->thresh > 0.0f && p->thresh < 1.0f)) return ROI_EINVAL;
+    } else {
+        return ROI_EINVAL;
+    }
+    if (p->dilate_radius < 0) return ROI_EINVAL;
+    if (p->se_shape != ROI_SE_SQUARE && p->se_shape != ROI_SE_DISC) return ROI_EINVAL;
+    if (p->flags & ~(uint32_t)(ROI_USE_INITIAL_FLOW | ROI_FP16_STORAGE)) return ROI_EINVAL;
+    if (p->winsize > 2 * IT_MAXR + 1) return ROI_EUNSUPPORTED;
+    if (p->dilate_radius > DIL_MAXR) return ROI_EUNSUPPORTED;
+    if (h > 32768 || w > 32768) return ROI_EUNSUPPORTED;
+    return ROI_OK;
+}
+
+size_t roi_workspace_size(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p)
+{
+    if (roi_validate(h, w, dtype, p) != ROI_OK) return 0;
+    if (h == 0 || w == 0) return HDR_BYTES;
+    return HDR_BYTES + make_plan(h, w, p).bytes;
+}
+
+roi_status roi_mask(const void *prev, const void *next, int32_t h, int32_t w, int64_t pitch, roi_dtype dtype,
+                    const roi_params *p, float *flow, uint8_t *mask, void *ws, size_t ws_bytes, void *stream)
+{
+    roi_status st = roi_validate(h, w, dtype, p);
+    if (st != ROI_OK) return st;
+    if (h == 0 || w == 0) return ROI_OK;
+    if (!prev || !next || !flow || !ws || pitch < w) return ROI_EINVAL;
+    if ((uintptr_t)ws % ALIGN) return ROI_EINVAL;
+    const Plan pl = make_plan(h, w, p);
+    if (ws_bytes < HDR_BYTES + pl.bytes) return ROI_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *base = (uint8_t *)ws + HDR_BYTES;
+    const void *frames[2] = {prev, next};
+    const int sets[2] = {0, 1};
+    st = enqueue_expand(pl, base, 2, frames, pitch, dtype, p, sets, s);
+    if (st != ROI_OK) return st;
+    return enqueue_flow(pl, base, (SelState *)ws, 0, 1, h, w, p, flow, mask, s);
+}
+
+roi_status roi_read_tau2(const void *ws, int32_t index, float *tau2_out, void *stream)
+{
+    if (!ws || !tau2_out || index < 0 || index >= MAX_BATCH) return ROI_EINVAL;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return ROI_EDEVICE;
+    SelState sst;
+    if (hipMemcpy(&sst, (const SelState *)ws + index, sizeof sst, hipMemcpyDeviceToHost) != hipSuccess)
+        return ROI_EDEVICE;
+    std::memcpy(tau2_out, &sst.tau2_bits, 4);
+    return ROI_OK;
+}
+
+roi_status roi_pyr_down(const float *src, int32_t h, int32_t w, float *dst, void *stream)
+{
+    if (!src || !dst || h < 0 || w < 0) return ROI_EINVAL;
+    if (h == 0 || w == 0) return ROI_OK;
+    PyrArgs a{};
+    a.src[0] = src;
+    a.dst[0] = dst;
+    a.src_pitch = w;
+    a.dst_pitch = (w + 1) / 2;
+    a.h = h;
+    a.w = w;
+    a.h2 = (h + 1) / 2;
+    a.w2 = (w + 1) / 2;
+    launch_pyr<float, float>(a, 1, (hipStream_t)stream);
+    LAUNCH_CHECK();
+    return ROI_OK;
+}
+
+roi_status roi_poly_expand(const void *img, int32_t h, int32_t w, int64_t pitch, roi_dtype dtype,
+                           const roi_params *p, float *coef, void *stream)
+{
+    roi_status st = roi_validate(h, w, dtype, p);
+    if (st != ROI_OK) return st;
+    if (h == 0 || w == 0) return ROI_OK;
+    if (!img || !coef || pitch < w) return ROI_EINVAL;
+    PolyArgs a{};
+    fill_poly(a, poly_consts(p->poly_n, p->poly_sigma));
+    a.src[0] = img;
+    a.dst[0] = coef;
+    a.src_pitch = pitch;
+    a.dc = dc_of(dtype);
+    a.dplane = (int64_t)h * w;
+    a.dpitch = w;
+    a.h = h;
+    a.w = w;
+    a.round16 = (p->flags & ROI_FP16_STORAGE) ? 1 : 0;
+    launch_poly_raw<float>(dtype, a, 1, (hipStream_t)stream);
+    LAUNCH_CHECK();
+    return ROI_OK;
+}
+
+// ---------------------------------------------------------------- batched
+
+size_t roi_batched_workspace_size(int32_t n, const roi_pair *pairs, roi_dtype dtype, const roi_params *p)
+{
+    if (n < 1 || n > MAX_BATCH || !pairs) return 0;
+    size_t total = HDR_BYTES;
+    for (int i = 0; i < n; ++i) {
+        if (roi_validate(pairs[i].h, pairs[i].w, dtype, p) != ROI_OK) return 0;
+        if (pairs[i].h > 0 && pairs[i].w > 0) total += make_plan(pairs[i].h, pairs[i].w, p).bytes;
+    }
+    return total;
+}
+
+static roi_status enqueue_pair(const roi_pair &q, roi_dtype dtype, const roi_params *p, uint8_t *base,
+                               SelState *slot, hipStream_t s)
+{
+    const Plan pl = make_plan(q.h, q.w, p);
+    const void *frames[2] = {q.prev, q.next};
+    const int sets[2] = {0, 1};
+    roi_status st = enqueue_expand(pl, base, 2, frames, q.pitch, dtype, p, sets, s);
+    if (st != ROI_OK) return st;
+    return enqueue_flow(pl, base, slot, 0, 1, q.h, q.w, p, q.flow, q.mask, s);
+}
+
+roi_status roi_mask_batched(int32_t n, const roi_pair *pairs, roi_dtype dtype, const roi_params *p, void *ws,
+                            size_t ws_bytes, void *stream)
+{
+    if (n < 1 || n > MAX_BATCH || !pairs || !p || !ws) return ROI_EINVAL;
+    if ((uintptr_t)ws % ALIGN) return ROI_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const roi_pair &q = pairs[i];
+        roi_status st = roi_validate(q.h, q.w, dtype, p);
+        if (st != ROI_OK) return st;
+        if (q.h == 0 || q.w == 0) continue;
+        if (!q.prev || !q.next || !q.flow || !q.mask || q.pitch < q.w) return ROI_EINVAL;
+    }
+    const size_t need = roi_batched_workspace_size(n, pairs, dtype, p);
+    if (need == 0) return ROI_EINVAL;
+    if (ws_bytes < need) return ROI_ENOMEM;
+    hipStream_t us = (hipStream_t)stream;
+
+    std::string key((const char *)pairs, sizeof(roi_pair) * n);
+    key.append((const char *)p, sizeof *p);
+    key.append((const char *)&dtype, sizeof dtype);
+    key.append((const char *)&ws, sizeof ws);
+    int dev = 0;
+    hipGetDevice(&dev);
+    key.append((const char *)&dev, sizeof dev);
+
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        const int naux = std::min(n, 8);
+        DeviceStreams *ds = device_streams(naux);
+        if (!ds) return ROI_EDEVICE;
+        hipStream_t cs = ds->cap;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return ROI_EDEVICE;
+        roi_status st = ROI_OK;
+        // fork: every auxiliary stream waits on the capture origin, pairs are
+        // spread over them so the graph holds independent per-pair chains
+        hipEventRecord(ds->ev[0], cs);
+        for (int k = 0; k < naux; ++k) hipStreamWaitEvent(ds->aux[k], ds->ev[0], 0);
+        uint8_t *base = (uint8_t *)ws + HDR_BYTES;
+        for (int i = 0; i < n && st == ROI_OK; ++i) {
+            const roi_pair &q = pairs[i];
+            if (q.h == 0 || q.w == 0) continue;
+            st = enqueue_pair(q, dtype, p, base, (SelState *)ws + i, ds->aux[i % naux]);
+            base += make_plan(q.h, q.w, p).bytes;
+        }
+        for (int k = 0; k < naux; ++k) {
+            hipEventRecord(ds->ev[k + 1], ds->aux[k]);
+            hipStreamWaitEvent(cs, ds->ev[k + 1], 0);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t ce = hipStreamEndCapture(cs, &graph);
+        if (st != ROI_OK || ce != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return st != ROI_OK ? st : ROI_EDEVICE;
+        }
+        GraphEntry e;
+        const hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ie != hipSuccess) return ROI_EDEVICE;
+        if (g_graphs.size() >= MAX_GRAPHS) {
+            auto lru = g_graphs.begin();
+            for (auto j = g_graphs.begin(); j != g_graphs.end(); ++j)
+                if (j->second.tick < lru->second.tick) lru = j;
+            hipGraphExecDestroy(lru->second.exec);
+            g_graphs.erase(lru);
+        }
+        it = g_graphs.emplace(key, e).first;
+    }
+    it->second.tick = ++g_tick;
+    if (hipGraphLaunch(it->second.exec, us) != hipSuccess) return ROI_EDEVICE;
+    return ROI_OK;
+}
+
+// ---------------------------------------------------------------- streaming
+
+struct roi_stream_ctx {
+    int32_t h, w;
+    roi_dtype dtype;
+    roi_params p;
+    Plan plan;
+    uint8_t *buf;   // HDR_BYTES of threshold state, then the plan
+    size_t bytes;
+    int primed;     // a previous frame's expansion is resident
+    int cur;        // expansion set holding the previous frame
+    int device;
+};
+
+size_t roi_stream_state_bytes(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p)
+{
+    if (roi_validate(h, w, dtype, p) != ROI_OK || h == 0 || w == 0) return 0;
+    return HDR_BYTES + make_plan(h, w, p).bytes;
+}
+
+roi_status roi_stream_create(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p, void **out_ctx)
+{
+    if (!out_ctx) return ROI_EINVAL;
+    *out_ctx = nullptr;
+    roi_status st = roi_validate(h, w, dtype, p);
+    if (st != ROI_OK) return st;
+    if (h == 0 || w == 0) return ROI_EINVAL;
+    roi_stream_ctx *c = new roi_stream_ctx();
+    c->h = h;
+    c->w = w;
+    c->dtype = dtype;
+    c->p = *p;
+    c->plan = make_plan(h, w, p);
+    c->bytes = HDR_BYTES + c->plan.bytes;
+    hipGetDevice(&c->device);
+    if (hipMalloc((void **)&c->buf, c->bytes) != hipSuccess) {
+        delete c;
+        return ROI_ENOMEM;
+    }
+    c->primed = 0;
+    c->cur = 0;
+    *out_ctx = c;
+    return ROI_OK;
+}
+
+roi_status roi_stream_reset(void *ctx)
+{
+    if (!ctx) return ROI_EINVAL;
+    ((roi_stream_ctx *)ctx)->primed = 0;
+    return ROI_OK;
+}
+
+void roi_stream_destroy(void *ctx)
+{
+    if (!ctx) return;
+    roi_stream_ctx *c = (roi_stream_ctx *)ctx;
+    hipFree(c->buf);
+    delete c;
+}
+
+static roi_status stream_push_one(roi_stream_ctx *c, const void *frame, int64_t pitch, float *flow, uint8_t *mask,
+                                  hipStream_t s)
+{
+    if (!frame || pitch < c->w) return ROI_EINVAL;
+    const int nxt = 1 - c->cur;
+    uint8_t *base = c->buf + HDR_BYTES;
+    const void *frames[1] = {frame};
+    const int sets[1] = {nxt};
+    roi_status st = enqueue_expand(c->plan, base, 1, frames, pitch, c->dtype, &c->p, sets, s);
+    if (st != ROI_OK) return st;
+    if (!c->primed) {
+        c->primed = 1;
+        c->cur = nxt;
+        return ROI_PRIMED;
+    }
+    if (!flow) return ROI_EINVAL;
+    st = enqueue_flow(c->plan, base, (SelState *)c->buf, c->cur, nxt, c->h, c->w, &c->p, flow, mask, s);
+    if (st != ROI_OK) return st;
+    c->cur = nxt;
+    return ROI_OK;
+}
+
+roi_status roi_stream_push(void *ctx, const void *frame, int64_t pitch, float *flow, uint8_t *mask, void *stream)
+{
+    if (!ctx) return ROI_EINVAL;
+    roi_stream_ctx *c = (roi_stream_ctx *)ctx;
+    if (c->primed && !flow) return ROI_EINVAL;
+    return stream_push_one(c, frame, pitch, flow, mask, (hipStream_t)stream);
+}
+
+roi_status roi_stream_push_many(int32_t n, void *const *ctxs, const void *const *frames, const int64_t *pitches,
+                                float *const *flows, uint8_t *const *masks, int32_t *status, void *stream)
+{
+    if (n < 1 || n > MAX_BATCH || !ctxs || !frames || !pitches || !flows || !masks || !status) return ROI_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        roi_stream_ctx *c = (roi_stream_ctx *)ctxs[i];
+        if (!c || !frames[i] || pitches[i] < c->w) return ROI_EINVAL;
+        if (c->primed && !flows[i]) return ROI_EINVAL;
+        if (c->dtype != ((roi_stream_ctx *)ctxs[0])->dtype ||
+            std::memcmp(&c->p, &((roi_stream_ctx *)ctxs[0])->p, sizeof(roi_params)) != 0)
+            return ROI_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < n; ++i) {
+        roi_status st = stream_push_one((roi_stream_ctx *)ctxs[i], frames[i], pitches[i], flows[i], masks[i], s);
+        if (st < 0) return st;
+        status[i] = st;
+    }
+    return ROI_OK;
+}
+
+// ---------------------------------------------------------------- timing
+
+void roi_timing_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.on = on != 0;
+}
+
+roi_status roi_timing_read(double *total_ms, int64_t *launches, int64_t *pixels, double *bytes)
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    for (const TimedLaunch &t : g_timing.pending) {
+        if (hipEventSynchronize(t.e1) != hipSuccess) return ROI_EDEVICE;
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, t.e0, t.e1) != hipSuccess) return ROI_EDEVICE;
+        g_timing.done_ms += ms;
+        g_timing.done_n += 1;
+        g_timing.done_px += t.px;
+        g_timing.done_bytes += t.bytes;
+        g_timing.pool.push_back(t.e0);
+        g_timing.pool.push_back(t.e1);
+    }
+    g_timing.pending.clear();
+    if (total_ms) *total_ms = g_timing.done_ms;
+    if (launches) *launches = g_timing.done_n;
+    if (pixels) *pixels = g_timing.done_px;
+    if (bytes) *bytes = g_timing.done_bytes;
+    return ROI_OK;
+}
+
+void roi_timing_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    for (const TimedLaunch &t : g_timing.pending) {
+        hipEventSynchronize(t.e1);
+        g_timing.pool.push_back(t.e0);
+        g_timing.pool.push_back(t.e1);
+    }
+    g_timing.pending.clear();
+    g_timing.done_ms = 0;
+    g_timing.done_bytes = 0;
+    g_timing.done_n = 0;
+    g_timing.done_px = 0;
+}
+
+void roi_autotune(int32_t mode)
+{
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    g_tune.mode = mode ? 1 : 0;
+    if (mode == 2) g_tune.best.clear();
+}
+
+roi_status roi_set_strip(int32_t strip)
+{
+    if (strip < 0 || (strip > 0 && strip % IT_CH != 0)) return ROI_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    g_tune.forced = strip;
+    return ROI_OK;
+}
+
+int32_t roi_tuned_strip(int32_t h, int32_t w, int32_t winsize, int32_t fp16)
+{
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    auto it = g_tune.best.find(std::make_tuple(h, w, winsize / 2, fp16 ? 1 : 0));
+    return it == g_tune.best.end() ? 0 : it->second;
+}
+
+const char *roi_status_str(roi_status s)
+{
+    switch (s) {
+    case ROI_OK: return "ok";
+    case ROI_PRIMED: return "primed (first frame of a stream stored)";
+    case ROI_EINVAL: return "invalid argument";
+    case ROI_ENOMEM: return "workspace too small or device allocation failed";
+    case ROI_EDEVICE: return "HIP launch or runtime failure";
+    case ROI_EUNSUPPORTED: return "unsupported parameter value";
+    }
+    return "unknown status";
+}
+
+} // extern "C"

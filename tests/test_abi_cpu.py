@@ -1,0 +1,132 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point the header declares, and validates requests exactly as
+documented (nothing reaches the device on these paths)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "flowroi.h")
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2511_14419_amd import build, flowroi
+    if build.stale():
+        build.build()
+    return flowroi
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(roi_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(F):
+    L = F.lib()
+    names = declared_functions()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(F.EXPORTED) == names
+
+
+def test_defaults(F):
+    p = F.default_params()
+    assert (p.levels, p.winsize, p.iterations, p.poly_n) == (3, 15, 3, 5)
+    assert abs(p.poly_sigma - 1.1) < 1e-6 and abs(p.eps - 1e-3) < 1e-9
+    assert (p.thresh_mode, p.thresh, p.dilate_radius, p.se_shape, p.flags) == (0, 1.0, 2, 0, 0)
+
+
+@pytest.mark.parametrize("kw,h,w,dtype,expect", [
+    ({}, 512, 512, 0, 0),
+    ({}, 0, 512, 1, 0),
+    ({}, -1, 5, 0, -1),
+    ({}, 8, 8, 3, -1),
+    ({"levels": 0}, 64, 64, 0, -1),
+    ({"levels": 11}, 64, 64, 0, -1),
+    ({"winsize": 14}, 64, 64, 0, -1),
+    ({"winsize": 17}, 64, 64, 0, -4),
+    ({"iterations": 0}, 64, 64, 0, -1),
+    ({"poly_n": 6}, 64, 64, 0, -1),
+    ({"poly_n": 9}, 64, 64, 0, -1),
+    ({"poly_sigma": 0.0}, 64, 64, 0, -1),
+    ({"eps": 0.0}, 64, 64, 0, -1),
+    ({"thresh": -0.5}, 64, 64, 0, -1),
+    ({"thresh_mode": 1, "thresh": 0.0}, 64, 64, 0, -1),
+    ({"thresh_mode": 1, "thresh": 1.0}, 64, 64, 0, -1),
+    ({"thresh_mode": 1, "thresh": 0.2}, 64, 64, 0, 0),
+    ({"thresh_mode": 2}, 64, 64, 0, -1),
+    ({"dilate_radius": -1}, 64, 64, 0, -1),
+    ({"dilate_radius": 33}, 64, 64, 0, -4),
+    ({"se_shape": 2}, 64, 64, 0, -1),
+    ({"flags": 8}, 64, 64, 0, -1),
+    ({"flags": 3}, 64, 64, 2, 0),
+    ({}, 40000, 64, 0, -4),
+])
+def test_validate(F, kw, h, w, dtype, expect):
+    assert F.validate(h, w, dtype, F.default_params(**kw)) == expect
+
+
+def test_workspace_size(F):
+    p = F.default_params()
+    a = F.lib().roi_workspace_size(512, 512, 0, ctypes.byref(p))
+    b = F.lib().roi_workspace_size(2048, 2048, 1, ctypes.byref(p))
+    assert 0 < a < b
+    half = F.default_params(flags=F.ROI_FP16_STORAGE)
+    assert F.lib().roi_workspace_size(2048, 2048, 1, ctypes.byref(half)) < b
+    assert F.lib().roi_workspace_size(64, 64, 0, ctypes.byref(F.default_params(levels=0))) == 0
+
+
+def test_roi_mask_rejects_before_launch(F):
+    L = F.lib()
+    p = F.default_params()
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x100000)
+    # null frame
+    assert L.roi_mask(None, fake, 64, 64, 64, 0, ctypes.byref(p), fake, fake, ws, 1 << 30, None) == F.ROI_EINVAL
+    # pitch < w
+    assert L.roi_mask(fake, fake, 64, 64, 63, 0, ctypes.byref(p), fake, fake, ws, 1 << 30, None) == F.ROI_EINVAL
+    # misaligned workspace
+    assert L.roi_mask(fake, fake, 64, 64, 64, 0, ctypes.byref(p), fake, fake, ctypes.c_void_p(0x100010),
+                      1 << 30, None) == F.ROI_EINVAL
+    # workspace too small
+    need = L.roi_workspace_size(64, 64, 0, ctypes.byref(p))
+    assert L.roi_mask(fake, fake, 64, 64, 64, 0, ctypes.byref(p), fake, fake, ws, need - 1, None) == F.ROI_ENOMEM
+    # bad params
+    bad = F.default_params(winsize=4)
+    assert L.roi_mask(fake, fake, 64, 64, 64, 0, ctypes.byref(bad), fake, fake, ws, 1 << 30, None) == F.ROI_EINVAL
+    # empty frame: no-op
+    assert L.roi_mask(None, None, 0, 64, 64, 0, ctypes.byref(p), None, None, None, 0, None) == F.ROI_OK
+
+
+def test_batched_and_stream_reject_before_launch(F):
+    L = F.lib()
+    p = F.default_params()
+    arr = (F.RoiPair * 1)()
+    arr[0] = F.RoiPair(0, 0x1000, 0x1000, 0x1000, 64, 64, 64)
+    assert L.roi_mask_batched(1, arr, 0, ctypes.byref(p), ctypes.c_void_p(0x100000), 1 << 30, None) == F.ROI_EINVAL
+    assert L.roi_mask_batched(0, arr, 0, ctypes.byref(p), ctypes.c_void_p(0x100000), 1 << 30, None) == F.ROI_EINVAL
+    assert L.roi_batched_workspace_size(257, arr, 0, ctypes.byref(p)) == 0
+    ctx = ctypes.c_void_p()
+    assert L.roi_stream_create(64, 64, 0, ctypes.byref(F.default_params(poly_n=4)), ctypes.byref(ctx)) == F.ROI_EINVAL
+    assert L.roi_stream_create(0, 64, 0, ctypes.byref(p), ctypes.byref(ctx)) == F.ROI_EINVAL
+    assert L.roi_stream_push(None, None, 64, None, None, None) == F.ROI_EINVAL
+    assert L.roi_stream_state_bytes(2048, 2048, 1, ctypes.byref(p)) > 0
+
+
+def test_strip_override_validation(F):
+    L = F.lib()
+    assert L.roi_set_strip(5) == F.ROI_EINVAL
+    assert L.roi_set_strip(-8) == F.ROI_EINVAL
+    assert L.roi_set_strip(0) == F.ROI_OK
+    assert L.roi_tuned_strip(123, 456, 15, 0) == 0
+
+
+def test_status_strings(F):
+    for s in (0, 1, -1, -2, -3, -4):
+        assert F.status_str(s)
+    assert F.status_str(99) == "unknown status"
