@@ -251,11 +251,30 @@ __device__ __forceinline__ void update_terms(const IterArgs &a, const TS *r1, co
     const float b1x = ld(r1, i1), b1y = ld(r1, i1 + P);
     const float a11 = ld(r1, i1 + 2 * P), a22 = ld(r1, i1 + 3 * P), a12 = ld(r1, i1 + 4 * P);
     const float2 d = prior_at(a, y, x);
-    const float xs = fminf(fmaxf(x + d.x, 0.f), (float)(a.w - 1));
-    const float ys = fminf(fmaxf(y + d.y, 0.f), (float)(a.h - 1));
-    const int x0 = (int)floorf(xs), y0 = (int)floorf(ys);
+    // Sample point x + d~ kept as integer pixel + fraction: an absolute FP32
+    // coordinate near x = 2000 only resolves 1.2e-4 px, which the solve can
+    // amplify past 1e-3 px at sensitive pixels. Clamping into the frame
+    // follows the real-valued point (outside -> edge pixel, zero weight).
+    const float dxc = fminf(fmaxf(d.x, -(float)(a.w + 1)), (float)(a.w + 1));
+    const float dyc = fminf(fmaxf(d.y, -(float)(a.h + 1)), (float)(a.h + 1));
+    const float flx = floorf(dxc), fly = floorf(dyc);
+    float fx = dxc - flx, fy = dyc - fly;
+    int x0 = x + (int)flx, y0 = y + (int)fly;
+    if (x0 < 0) {
+        x0 = 0;
+        fx = 0.f;
+    } else if (x0 > a.w - 1 || (x0 == a.w - 1 && fx > 0.f)) {
+        x0 = a.w - 1;
+        fx = 0.f;
+    }
+    if (y0 < 0) {
+        y0 = 0;
+        fy = 0.f;
+    } else if (y0 > a.h - 1 || (y0 == a.h - 1 && fy > 0.f)) {
+        y0 = a.h - 1;
+        fy = 0.f;
+    }
     const int x1 = min(x0 + 1, a.w - 1), y1 = min(y0 + 1, a.h - 1);
-    const float fx = xs - x0, fy = ys - y0;
     const size_t q00 = (size_t)y0 * a.rpitch + x0, q01 = (size_t)y0 * a.rpitch + x1;
     const size_t q10 = (size_t)y1 * a.rpitch + x0, q11 = (size_t)y1 * a.rpitch + x1;
     float c[5];
