@@ -49,7 +49,8 @@ size_t dtype_bytes(roi_dtype d) { return d == ROI_U8 ? 1 : (d == ROI_U16 ? 2 : 4
 struct Level {
     int h, w, pitch;  // pitch in elements, a multiple of 64
     size_t img[2];    // pyramid image of each frame (levels >= 1)
-    size_t r[2];      // 5-plane expansion of each frame
+    size_t r4[2];     // packed expansion of each frame: (b_x, b_y, A_xx, A_yy) per pixel
+    size_t r1[2];     // and A_xy per pixel
     size_t fa, fb;    // flow ping-pong (fb unused at level 0: the caller's buffer)
 };
 
@@ -86,7 +87,8 @@ Plan make_plan(int h, int w, const roi_params *p)
         const size_t plane = (size_t)v.h * v.pitch;
         for (int f = 0; f < 2; ++f) {
             v.img[f] = l > 0 ? take(plane * pl.is) : 0;
-            v.r[f] = take(5 * plane * pl.ts);
+            v.r4[f] = take(4 * plane * pl.ts);
+            v.r1[f] = take(plane * pl.ts);
         }
         v.fa = take(plane * sizeof(float2));
         v.fb = l > 0 ? take(plane * sizeof(float2)) : 0;
@@ -256,8 +258,10 @@ roi_status enqueue_expand(const Plan &pl, uint8_t *base, int nf, const void *con
         fill_poly(a, pc);
         for (int f = 0; f < nf; ++f) {
             a.src[f] = l == 0 ? frames[f] : (const void *)(base + v.img[set[f]]);
-            a.dst[f] = base + v.r[set[f]];
+            a.dst[f] = base + v.r4[set[f]];
+            a.dst1[f] = base + v.r1[set[f]];
         }
+        a.packed = 1;
         a.src_pitch = l == 0 ? pitch : v.pitch;
         a.dc = l == 0 ? dc_of(dt) : 0.0f;
         a.dplane = (int64_t)v.h * v.pitch;
@@ -301,22 +305,30 @@ int heuristic_strip(int h, int w)
     return strip;
 }
 
-template <typename TS>
-void launch_iter_t(const IterArgs &a, int strip, hipStream_t s)
+template <typename TS, int PRIOR>
+void launch_iter_p(const IterArgs &a, int strip, hipStream_t s)
 {
     const int nx = (a.w + IT_TW - 1) / IT_TW, ny = (a.h + strip - 1) / strip;
     const int nt = nx * ny;
-    dim3 g(nt), b(256);
+    dim3 g(nt), b(IT_THREADS);
     switch (a.R) {
-    case 0: hipLaunchKernelGGL((k_iter<TS, 0>), g, b, 0, s, a, strip, nx, nt); break;
-    case 1: hipLaunchKernelGGL((k_iter<TS, 1>), g, b, 0, s, a, strip, nx, nt); break;
-    case 2: hipLaunchKernelGGL((k_iter<TS, 2>), g, b, 0, s, a, strip, nx, nt); break;
-    case 3: hipLaunchKernelGGL((k_iter<TS, 3>), g, b, 0, s, a, strip, nx, nt); break;
-    case 4: hipLaunchKernelGGL((k_iter<TS, 4>), g, b, 0, s, a, strip, nx, nt); break;
-    case 5: hipLaunchKernelGGL((k_iter<TS, 5>), g, b, 0, s, a, strip, nx, nt); break;
-    case 6: hipLaunchKernelGGL((k_iter<TS, 6>), g, b, 0, s, a, strip, nx, nt); break;
-    default: hipLaunchKernelGGL((k_iter<TS, 7>), g, b, 0, s, a, strip, nx, nt); break;
+    case 0: hipLaunchKernelGGL((k_iter<TS, 0, PRIOR>), g, b, 0, s, a, strip, nx, nt); break;
+    case 1: hipLaunchKernelGGL((k_iter<TS, 1, PRIOR>), g, b, 0, s, a, strip, nx, nt); break;
+    case 2: hipLaunchKernelGGL((k_iter<TS, 2, PRIOR>), g, b, 0, s, a, strip, nx, nt); break;
+    case 3: hipLaunchKernelGGL((k_iter<TS, 3, PRIOR>), g, b, 0, s, a, strip, nx, nt); break;
+    case 4: hipLaunchKernelGGL((k_iter<TS, 4, PRIOR>), g, b, 0, s, a, strip, nx, nt); break;
+    case 5: hipLaunchKernelGGL((k_iter<TS, 5, PRIOR>), g, b, 0, s, a, strip, nx, nt); break;
+    case 6: hipLaunchKernelGGL((k_iter<TS, 6, PRIOR>), g, b, 0, s, a, strip, nx, nt); break;
+    default: hipLaunchKernelGGL((k_iter<TS, 7, PRIOR>), g, b, 0, s, a, strip, nx, nt); break;
     }
+}
+
+template <typename TS>
+void launch_iter_t(const IterArgs &a, int strip, hipStream_t s)
+{
+    if (a.prior == PRIOR_ZERO) launch_iter_p<TS, PRIOR_ZERO>(a, strip, s);
+    else if (a.prior == PRIOR_PLAIN) launch_iter_p<TS, PRIOR_PLAIN>(a, strip, s);
+    else launch_iter_p<TS, PRIOR_UPSAMPLE>(a, strip, s);
 }
 
 void launch_iter_raw(const IterArgs &a, bool fp16, int strip, hipStream_t s)
@@ -436,9 +448,10 @@ roi_status enqueue_flow(const Plan &pl, uint8_t *base, SelState *slot, int s1, i
         int prev_pitch = 0;
         for (int it = 0; it < n; ++it) {
             IterArgs a{};
-            a.r1 = base + v.r[s1];
-            a.r2 = base + v.r[s2];
-            a.rplane = (int64_t)v.h * v.pitch;
+            a.p4[0] = base + v.r4[s1];
+            a.p1[0] = base + v.r1[s1];
+            a.p4[1] = base + v.r4[s2];
+            a.p1[1] = base + v.r1[s2];
             a.rpitch = v.pitch;
             a.h = v.h;
             a.w = v.w;
@@ -608,6 +621,9 @@ roi_status roi_validate(int32_t h, int32_t w, roi_dtype dtype, const roi_params 
     if (p->winsize > 2 * IT_MAXR + 1) return ROI_EUNSUPPORTED;
     if (p->dilate_radius > DIL_MAXR) return ROI_EUNSUPPORTED;
     if (h > 32768 || w > 32768) return ROI_EUNSUPPORTED;
+    // the iteration kernel addresses a level's packed plane (16 B per pixel
+    // of a 64-aligned row) with 32-bit byte offsets
+    if ((uint64_t)h * align_up((size_t)w, 64) * 16 >= (1ull << 32)) return ROI_EUNSUPPORTED;
     return ROI_OK;
 }
 

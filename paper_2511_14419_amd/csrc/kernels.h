@@ -42,6 +42,63 @@ __device__ __forceinline__ void std_(double *p, size_t i, double v) { p[i] = v; 
 __device__ __forceinline__ void std_(float *p, size_t i, double v) { p[i] = (float)v; }
 __device__ __forceinline__ void std_(__half *p, size_t i, double v) { p[i] = __float2half((float)v); }
 
+// Raw buffer descriptors (gfx9 family: dword3 = 0x00020000). Loads through
+// them take a 32-bit byte offset in a VGPR against a scalar base, which keeps
+// address arithmetic of the gathers off the vector ALU; out-of-range offsets
+// read 0 instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float4 bload4(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float bload1(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ float bload1h(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)));
+}
+__device__ __forceinline__ float4 bload4h(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    const uint2 u = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    const __half2 lo = __builtin_bit_cast(__half2, u.x), hi = __builtin_bit_cast(__half2, u.y);
+    return make_float4(__low2float(lo), __high2float(lo), __low2float(hi), __high2float(hi));
+}
+
+// Packed storage of one frame's expansion: P4 = (b_x, b_y, A_xx, A_yy) per
+// pixel (float4, or 4 x FP16), P1 = A_xy (float or FP16). Both h x pitch.
+template <typename TS> struct Packed;
+template <> struct Packed<float> {
+    static constexpr uint32_t B4 = 16, B1 = 4;
+    __device__ static float4 load4(__amdgpu_buffer_rsrc_t r, uint32_t px) { return bload4(r, px * B4); }
+    __device__ static float load1(__amdgpu_buffer_rsrc_t r, uint32_t px) { return bload1(r, px * B1); }
+    __device__ static void store(void *p4, void *p1, size_t px, const float o[5])
+    {
+        ((float4 *)p4)[px] = make_float4(o[0], o[1], o[2], o[3]);
+        ((float *)p1)[px] = o[4];
+    }
+};
+template <> struct Packed<__half> {
+    static constexpr uint32_t B4 = 8, B1 = 2;
+    __device__ static float4 load4(__amdgpu_buffer_rsrc_t r, uint32_t px) { return bload4h(r, px * B4); }
+    __device__ static float load1(__amdgpu_buffer_rsrc_t r, uint32_t px) { return bload1h(r, px * B1); }
+    __device__ static void store(void *p4, void *p1, size_t px, const float o[5])
+    {
+        const __half2 lo = __floats2half2_rn(o[0], o[1]), hi = __floats2half2_rn(o[2], o[3]);
+        ((uint2 *)p4)[px] = make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+        ((__half *)p1)[px] = __float2half(o[4]);
+    }
+};
+
 // FP16 rounding of a value kept in an FP32 buffer (stage entry points).
 __device__ __forceinline__ float round16(float v) { return __half2float(__float2half(v)); }
 
@@ -106,11 +163,13 @@ struct PolyArgs {
     const void *src[2];
     int64_t src_pitch;
     float dc;
-    void *dst[2];       // 5 planes each: b_x, b_y, A_xx, A_yy, A_xy
-    int64_t dplane;     // elements between planes
+    void *dst[2];       // planar: 5 float planes b_x, b_y, A_xx, A_yy, A_xy; packed: P4
+    void *dst1[2];      // packed: P1 (A_xy)
+    int64_t dplane;     // planar: elements between planes
     int32_t dpitch;
     int32_t h, w, n;    // n = poly_n / 2
-    int32_t round16;
+    int32_t round16;    // planar: values rounded to FP16 precision
+    int32_t packed;     // 1: Packed<TOut> layout (P4, P1); 0: 5 float planes
     // vertical kernels over the row offset t = -n..n:
     //   kv0 = a(t), kv1 = t a(t), kv2 = (t^2 - m2/m0) a(t)
     double kv0[2 * PE_MAXN + 1], kv1[2 * PE_MAXN + 1], kv2[2 * PE_MAXN + 1];
@@ -135,7 +194,6 @@ __global__ __launch_bounds__(256) void k_polyexp(PolyArgs a)
     __shared__ double s[SH][SW + 1];
     __shared__ double vr[3][PE_TH][SW + 1];
     const TIn *src = (const TIn *)a.src[blockIdx.z];
-    TOut *dst = (TOut *)a.dst[blockIdx.z];
     const int n = a.n, sw = PE_TW + 2 * n, sh = PE_TH + 2 * n;
     const int ox0 = blockIdx.x * PE_TW, oy0 = blockIdx.y * PE_TH;
     for (int i = threadIdx.x; i < sh * sw; i += 256) {
@@ -172,10 +230,14 @@ __global__ __launch_bounds__(256) void k_polyexp(PolyArgs a)
             ayy += a.hyy[t] * v2;
         }
         float o[5] = {(float)bx, (float)by, (float)axx, (float)ayy, (float)axy};
-        if (a.round16)
-            for (int k = 0; k < 5; ++k) o[k] = round16(o[k]);
         const size_t q = (size_t)y * a.dpitch + x;
-        for (int k = 0; k < 5; ++k) st(dst, q + k * a.dplane, o[k]);
+        if (a.packed) {
+            Packed<TOut>::store(a.dst[blockIdx.z], a.dst1[blockIdx.z], q, o);
+        } else {
+            if (a.round16)
+                for (int k = 0; k < 5; ++k) o[k] = round16(o[k]);
+            for (int k = 0; k < 5; ++k) st((float *)a.dst[blockIdx.z], q + k * a.dplane, o[k]);
+        }
     }
 }
 
@@ -203,11 +265,10 @@ constexpr int IT_TW = 64, IT_MAXR = 7;
 enum { PRIOR_ZERO = 0, PRIOR_PLAIN = 1, PRIOR_UPSAMPLE = 2 };
 
 struct IterArgs {
-    const void *r1, *r2;     // expansions of prev and next (5 planes each)
-    int64_t rplane;
-    int32_t rpitch;
+    const void *p4[2], *p1[2]; // packed expansions of prev [0] and next [1]
+    int32_t rpitch;            // pixels per row of the packed planes
     int32_t h, w;
-    int32_t prior;           // PRIOR_*
+    int32_t prior;           // PRIOR_* (the kernel is specialised on it)
     const float2 *fin;       // prior flow (PLAIN: this level; UPSAMPLE: coarser level)
     int32_t fin_pitch, hc, wc;
     float2 *fout;
@@ -223,74 +284,113 @@ __device__ __forceinline__ float bilerp(float p00, float p01, float p10, float p
     return (1.f - fy) * ((1.f - fx) * p00 + fx * p01) + fy * ((1.f - fx) * p10 + fx * p11);
 }
 
-__device__ __forceinline__ float2 prior_at(const IterArgs &a, int y, int x)
+// Buffer descriptors of one launch (uniform across the grid).
+struct IterRes {
+    __amdgpu_buffer_rsrc_t p4a, p1a, p4b, p1b, fin;
+};
+
+// Loads that need nothing but the pixel position: prev's coefficients at x
+// and the raw prior-flow samples (one vector, or the four coarse-grid
+// neighbours when the prior is the upsampled coarser flow).
+struct PxIn {
+    float4 q1;   // b1x, b1y, a11, a22
+    float a12;
+    float2 p00, p01, p10, p11;
+};
+
+// The bilinear gather of next's coefficients around x + d~.
+struct PxG {
+    float4 v00, v01, v10, v11;
+    float w00, w01, w10, w11;
+    float fx, fy;
+    float2 d;
+};
+
+template <typename TS, int PRIOR>
+__device__ __forceinline__ PxIn load_in(const IterArgs &a, const IterRes &rs, int y, int x)
 {
-    if (a.prior == PRIOR_ZERO) return make_float2(0.f, 0.f);
-    if (a.prior == PRIOR_PLAIN) return a.fin[(size_t)y * a.fin_pitch + x];
-    // pixel (y, x) of this level sits at (y/2, x/2) of the coarser grid
-    float xs = fminf(x * 0.5f, (float)(a.wc - 1)), ys = fminf(y * 0.5f, (float)(a.hc - 1));
-    const int x0 = (int)xs, y0 = (int)ys;
-    const int x1 = min(x0 + 1, a.wc - 1), y1 = min(y0 + 1, a.hc - 1);
-    const float fx = xs - x0, fy = ys - y0;
-    const float2 p00 = a.fin[(size_t)y0 * a.fin_pitch + x0], p01 = a.fin[(size_t)y0 * a.fin_pitch + x1];
-    const float2 p10 = a.fin[(size_t)y1 * a.fin_pitch + x0], p11 = a.fin[(size_t)y1 * a.fin_pitch + x1];
-    return make_float2(2.f * bilerp(p00.x, p01.x, p10.x, p11.x, fx, fy),
-                       2.f * bilerp(p00.y, p01.y, p10.y, p11.y, fx, fy));
+    using PK = Packed<TS>;
+    PxIn r;
+    const uint32_t c = (uint32_t)y * a.rpitch + x;
+    r.q1 = PK::load4(rs.p4a, c);
+    r.a12 = PK::load1(rs.p1a, c);
+    if (PRIOR == PRIOR_PLAIN) {
+        r.p00 = bload2(rs.fin, ((uint32_t)y * a.fin_pitch + x) * 8u);
+    } else if (PRIOR == PRIOR_UPSAMPLE) {
+        // pixel (y, x) of this level sits at (y/2, x/2) of the coarser grid
+        const int xc = min(x >> 1, a.wc - 1), yc = min(y >> 1, a.hc - 1);
+        const int x1 = min(xc + 1, a.wc - 1), y1 = min(yc + 1, a.hc - 1);
+        r.p00 = bload2(rs.fin, ((uint32_t)yc * a.fin_pitch + xc) * 8u);
+        r.p01 = bload2(rs.fin, ((uint32_t)yc * a.fin_pitch + x1) * 8u);
+        r.p10 = bload2(rs.fin, ((uint32_t)y1 * a.fin_pitch + xc) * 8u);
+        r.p11 = bload2(rs.fin, ((uint32_t)y1 * a.fin_pitch + x1) * 8u);
+    }
+    return r;
+}
+
+template <int PRIOR>
+__device__ __forceinline__ float2 prior_of(const IterArgs &a, const PxIn &in, int y, int x)
+{
+    if (PRIOR == PRIOR_ZERO) return make_float2(0.f, 0.f);
+    if (PRIOR == PRIOR_PLAIN) return in.p00;
+    // 2 x bilinear(coarse, x/2, y/2), the point clamped into the coarse grid
+    // (half-integer coordinates: exact in FP32)
+    const float fx = (x >> 1) < a.wc - 1 ? 0.5f * (x & 1) : 0.f;
+    const float fy = (y >> 1) < a.hc - 1 ? 0.5f * (y & 1) : 0.f;
+    return make_float2(2.f * bilerp(in.p00.x, in.p01.x, in.p10.x, in.p11.x, fx, fy),
+                       2.f * bilerp(in.p00.y, in.p01.y, in.p10.y, in.p11.y, fx, fy));
+}
+
+// Sample point x + d~ kept as integer pixel + fraction: an absolute FP32
+// coordinate near x = 2000 only resolves 1.2e-4 px, which the solve can
+// amplify past 1e-3 px at sensitive pixels. Clamping into the frame follows
+// the real-valued point (outside -> edge pixel, zero weight). A NaN prior
+// clamps to the frame's left/top edge, so every load stays in bounds.
+template <typename TS, int PRIOR>
+__device__ __forceinline__ PxG issue_gather(const IterArgs &a, const IterRes &rs, const PxIn &in, int y, int x)
+{
+    using PK = Packed<TS>;
+    PxG g;
+    g.d = prior_of<PRIOR>(a, in, y, x);
+    // clamping x + d~ into [0, w-1] is clamping d~ into [-x, w-1-x] (integer
+    // bounds: exact); afterwards x0 = w-1 implies a zero fraction
+    const float dxc = fminf(fmaxf(g.d.x, (float)-x), (float)(a.w - 1 - x));
+    const float dyc = fminf(fmaxf(g.d.y, (float)-y), (float)(a.h - 1 - y));
+    const float flx = floorf(dxc), fly = floorf(dyc);
+    g.fx = dxc - flx;
+    g.fy = dyc - fly;
+    const int x0 = x + (int)flx, y0 = y + (int)fly;
+    const uint32_t dxi = x0 < a.w - 1 ? 1u : 0u, dyi = y0 < a.h - 1 ? (uint32_t)a.rpitch : 0u;
+    const uint32_t c00 = (uint32_t)y0 * a.rpitch + x0;
+    g.v00 = PK::load4(rs.p4b, c00);
+    g.v01 = PK::load4(rs.p4b, c00 + dxi);
+    g.v10 = PK::load4(rs.p4b, c00 + dyi);
+    g.v11 = PK::load4(rs.p4b, c00 + dyi + dxi);
+    g.w00 = PK::load1(rs.p1b, c00);
+    g.w01 = PK::load1(rs.p1b, c00 + dxi);
+    g.w10 = PK::load1(rs.p1b, c00 + dyi);
+    g.w11 = PK::load1(rs.p1b, c00 + dyi + dxi);
+    return g;
 }
 
 // Per-pixel normal-equation terms G = A^T A (g11, g12, g22) and h = A^T db
-// for the prior displacement d~ at (y, x):
-//   A  = (A1(x) + A2(x + d~)) / 2,  db = -(b2(x + d~) - b1(x)) / 2 + A d~,
-// next's coefficients sampled bilinearly at x + d~ clamped into the frame.
-template <typename TS>
-__device__ __forceinline__ void update_terms(const IterArgs &a, const TS *r1, const TS *r2, int y, int x,
-                                             float g[5])
+// for the prior displacement d~:
+//   A  = (A1(x) + A2(x + d~)) / 2,  db = -(b2(x + d~) - b1(x)) / 2 + A d~.
+__device__ __forceinline__ void update_terms(const PxIn &in, const PxG &g, float o[5])
 {
-    const size_t P = (size_t)a.rplane;
-    const size_t i1 = (size_t)y * a.rpitch + x;
-    const float b1x = ld(r1, i1), b1y = ld(r1, i1 + P);
-    const float a11 = ld(r1, i1 + 2 * P), a22 = ld(r1, i1 + 3 * P), a12 = ld(r1, i1 + 4 * P);
-    const float2 d = prior_at(a, y, x);
-    // Sample point x + d~ kept as integer pixel + fraction: an absolute FP32
-    // coordinate near x = 2000 only resolves 1.2e-4 px, which the solve can
-    // amplify past 1e-3 px at sensitive pixels. Clamping into the frame
-    // follows the real-valued point (outside -> edge pixel, zero weight).
-    const float dxc = fminf(fmaxf(d.x, -(float)(a.w + 1)), (float)(a.w + 1));
-    const float dyc = fminf(fmaxf(d.y, -(float)(a.h + 1)), (float)(a.h + 1));
-    const float flx = floorf(dxc), fly = floorf(dyc);
-    float fx = dxc - flx, fy = dyc - fly;
-    int x0 = x + (int)flx, y0 = y + (int)fly;
-    if (x0 < 0) {
-        x0 = 0;
-        fx = 0.f;
-    } else if (x0 > a.w - 1 || (x0 == a.w - 1 && fx > 0.f)) {
-        x0 = a.w - 1;
-        fx = 0.f;
-    }
-    if (y0 < 0) {
-        y0 = 0;
-        fy = 0.f;
-    } else if (y0 > a.h - 1 || (y0 == a.h - 1 && fy > 0.f)) {
-        y0 = a.h - 1;
-        fy = 0.f;
-    }
-    const int x1 = min(x0 + 1, a.w - 1), y1 = min(y0 + 1, a.h - 1);
-    const size_t q00 = (size_t)y0 * a.rpitch + x0, q01 = (size_t)y0 * a.rpitch + x1;
-    const size_t q10 = (size_t)y1 * a.rpitch + x0, q11 = (size_t)y1 * a.rpitch + x1;
-    float c[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const TS *p = r2 + k * P;
-        c[k] = bilerp(ld(p, q00), ld(p, q01), ld(p, q10), ld(p, q11), fx, fy);
-    }
-    const float A11 = 0.5f * (a11 + c[2]), A22 = 0.5f * (a22 + c[3]), A12 = 0.5f * (a12 + c[4]);
-    const float dbx = -0.5f * (c[0] - b1x) + A11 * d.x + A12 * d.y;
-    const float dby = -0.5f * (c[1] - b1y) + A12 * d.x + A22 * d.y;
-    g[0] = A11 * A11 + A12 * A12;
-    g[1] = A12 * (A11 + A22);
-    g[2] = A12 * A12 + A22 * A22;
-    g[3] = A11 * dbx + A12 * dby;
-    g[4] = A12 * dbx + A22 * dby;
+    const float b2x = bilerp(g.v00.x, g.v01.x, g.v10.x, g.v11.x, g.fx, g.fy);
+    const float b2y = bilerp(g.v00.y, g.v01.y, g.v10.y, g.v11.y, g.fx, g.fy);
+    const float c11 = bilerp(g.v00.z, g.v01.z, g.v10.z, g.v11.z, g.fx, g.fy);
+    const float c22 = bilerp(g.v00.w, g.v01.w, g.v10.w, g.v11.w, g.fx, g.fy);
+    const float c12 = bilerp(g.w00, g.w01, g.w10, g.w11, g.fx, g.fy);
+    const float A11 = 0.5f * (in.q1.z + c11), A22 = 0.5f * (in.q1.w + c22), A12 = 0.5f * (in.a12 + c12);
+    const float dbx = -0.5f * (b2x - in.q1.x) + A11 * g.d.x + A12 * g.d.y;
+    const float dby = -0.5f * (b2y - in.q1.y) + A12 * g.d.x + A22 * g.d.y;
+    o[0] = A11 * A11 + A12 * A12;
+    o[1] = A12 * (A11 + A22);
+    o[2] = A12 * A12 + A22 * A22;
+    o[3] = A11 * dbx + A12 * dby;
+    o[4] = A12 * dbx + A22 * dby;
 }
 
 // Solve of the pooled 2x2 system G d = h (g11, g12, g22, h1, h2):
@@ -300,31 +400,130 @@ __device__ __forceinline__ float2 solve2(float g11, float g12, float g22, float 
     const float tr = g11 + g22;
     if (tr == 0.f) return make_float2(0.f, 0.f);
     const float det = g11 * g22 - g12 * g12;
-    const float den = fmaxf(det, eps * tr * tr);
-    return make_float2((g22 * h1 - g12 * h2) / den, (g11 * h2 - g12 * h1) / den);
+    const float inv = 1.0f / fmaxf(det, eps * tr * tr);
+    return make_float2((g22 * h1 - g12 * h2) * inv, (g11 * h2 - g12 * h1) * inv);
 }
 
-// Strip walker. A workgroup owns IT_TW output columns and a strip of rows
-// [y_begin, y_end); it walks down in chunks of IT_CH rows:
-//   1. per-pixel terms for IT_CH new rows over IT_TW + 2R columns -> LDS;
-//   2. horizontal window sums of those rows -> a ring of IT_CH + 2R rows;
-//   3. vertical window sums for the output rows whose window is complete,
-//      then the solve; each thread finishes two vertically adjacent pixels.
+// Strip walker. A workgroup of 320 threads owns IT_TW output columns and a
+// strip of rows [ys, ye) (ys a multiple of 8); it walks down in chunks of
+// IT_CH computed rows:
+//   1. per-pixel terms of the chunk's rows over IT_TW + 2R columns -> LDS;
+//   2. horizontal window sums of those rows (task = channel, row, 8-column
+//      segment) -> LDS;
+//   3a. thread (channel, column) appends its 8 new horizontal sums to a
+//      register ring and forms the vertical sums of one aligned group of 8
+//      output rows -> LDS;
+//   3b. the 2x2 solves of those 512 pixels.
+// Computed rows start PRE rows above ys - R so that output groups sit at
+// multiples of 8; every window sum is either taken directly (first of an
+// 8-column segment / 8-row group) or slid by one from its neighbour, in a
+// pattern fixed by absolute positions, so results do not depend on the
+// strip height. The chunk loop is unrolled over the NPH ring phases, which
+// makes every register-ring index a compile-time constant.
 // Replicated borders: out-of-frame rows/columns take the edge pixel's terms.
-// Window sums are exact sums of 2R+1 terms in a fixed order that depends
-// only on absolute pixel positions (segments of 16 columns, row pairs
-// starting at even rows), so results do not depend on the strip height.
-// grid: (ceil(w / IT_TW) * ceil(h / strip) remapped so that consecutive
-// strips land on the same XCD), block 256.
-constexpr int IT_CH = 8, IT_SEG = 16;
+constexpr int IT_CH = 8, IT_SEG = 8, IT_THREADS = 320, IT_HSP = IT_TW + 1;
 
-template <typename TS, int R>
-__global__ __launch_bounds__(256) void k_iter(IterArgs a, int32_t strip, int32_t nx, int32_t ntiles)
+template <int R> struct IterGeom {
+    static constexpr int CW = IT_TW + 2 * R;                      // columns of per-pixel terms
+    static constexpr int PRE = (IT_CH - (2 * R) % IT_CH) % IT_CH; // extra rows above ys - R
+    static constexpr int J0 = (2 * R + PRE) / IT_CH;              // chunks before the first output group
+    static constexpr int NPH = J0 + 1;                            // ring phases
+    static constexpr int RING = IT_CH * NPH;                      // ring length (>= IT_CH + 2R)
+    static constexpr int NR1 = (IT_CH * CW + IT_THREADS - 1) / IT_THREADS; // step-1 pixels per thread
+    static constexpr int GH = 5 * IT_CH * CW;                     // floats of step-1 terms (reused by 3a)
+    static constexpr int HN = 5 * IT_CH * IT_HSP;                 // floats of new horizontal sums
+};
+
+struct IterCtx {
+    int x0, ys, ye, y_first, nch;
+};
+
+// One chunk j (ring phase P = j mod NPH) of computed rows [y_first + 8 j, + 8).
+template <typename TS, int R, int PRIOR, int P>
+__device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs, float *lds, const IterCtx &cx, int j,
+                                           const int (&rr)[IterGeom<R>::NR1], const int (&cc)[IterGeom<R>::NR1],
+                                           const bool (&live)[IterGeom<R>::NR1], const int (&xs_)[IterGeom<R>::NR1],
+                                           float (&ring)[IterGeom<R>::RING])
 {
-    constexpr int CW = IT_TW + 2 * R;   // columns of per-pixel terms
-    constexpr int RING = IT_CH + 2 * R; // rows of horizontal sums kept
-    __shared__ float gh[5][IT_CH][CW];
-    __shared__ float hs[5][RING][IT_TW];
+    using G = IterGeom<R>;
+    float *gh = lds;          // [5][IT_CH][CW]; after step 2 reused as vs [5][IT_CH][IT_TW]
+    float *hn = lds + G::GH;  // [5][IT_CH][IT_HSP]
+    const int t = threadIdx.x;
+    const int cy = cx.y_first + IT_CH * j;
+    // 1. per-pixel terms of rows [cy, cy + IT_CH)
+#pragma unroll
+    for (int m = 0; m < G::NR1; ++m) {
+        if (live[m]) {
+            const int y = clampi(cy + rr[m], 0, a.h - 1);
+            const PxIn in = load_in<TS, PRIOR>(a, rs, y, xs_[m]);
+            const PxG g = issue_gather<TS, PRIOR>(a, rs, in, y, xs_[m]);
+            float o[5];
+            update_terms(in, g, o);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) gh[(k * IT_CH + rr[m]) * G::CW + cc[m]] = o[k];
+        }
+    }
+    __syncthreads();
+    // 2. horizontal sums: task = (channel, row, 8-column segment)
+    {
+        const int k = t >> 6, r = (t >> 3) & 7, sg = t & 7;
+        const float *src = gh + (k * IT_CH + r) * G::CW + sg * IT_SEG;
+        float v[IT_SEG + 2 * R];
+#pragma unroll
+        for (int q = 0; q < IT_SEG + 2 * R; ++q) v[q] = src[q];
+        float *dst = hn + (k * IT_CH + r) * IT_HSP + sg * IT_SEG;
+        float sum = 0.f;
+#pragma unroll
+        for (int u = 0; u <= 2 * R; ++u) sum += v[u];
+        dst[0] = sum;
+#pragma unroll
+        for (int q = 1; q < IT_SEG; ++q) {
+            sum = sum - v[q - 1] + v[q + 2 * R];
+            dst[q] = sum;
+        }
+    }
+    __syncthreads();
+    // 3a. thread (channel k, column c): ring update, vertical sums of the group
+    const int grp = j - G::J0; // output group: rows ys + 8 grp ... + 7
+    const int k = t >> 6, c = t & 63;
+#pragma unroll
+    for (int i = 0; i < IT_CH; ++i) ring[IT_CH * P + i] = hn[(k * IT_CH + i) * IT_HSP + c];
+    if (grp < 0) return; // (uniform) the ring is still filling
+    {
+        // ring position of row (group start - R)
+        constexpr int S0 = ((IT_CH * P - IT_CH * G::J0 + G::PRE) % G::RING + G::RING) % G::RING;
+        float sum = 0.f;
+#pragma unroll
+        for (int u = 0; u <= 2 * R; ++u) sum += ring[(S0 + u) % G::RING];
+        float *vs = gh + k * IT_CH * IT_TW + c;
+        vs[0] = sum;
+#pragma unroll
+        for (int i = 1; i < IT_CH; ++i) {
+            sum = sum - ring[(S0 + i - 1) % G::RING] + ring[(S0 + i + 2 * R) % G::RING];
+            vs[i * IT_TW] = sum;
+        }
+    }
+    __syncthreads();
+    // 3b. solves of the group's 512 pixels
+    for (int px = t; px < IT_CH * IT_TW; px += IT_THREADS) {
+        const int i = px >> 6, cc2 = px & 63;
+        const int oy = cx.ys + IT_CH * grp + i, x = cx.x0 + cc2;
+        if (oy < cx.ye && x < a.w) {
+            const float *vv = gh + i * IT_TW + cc2;
+            const float2 d = solve2(vv[0], vv[IT_CH * IT_TW], vv[2 * IT_CH * IT_TW], vv[3 * IT_CH * IT_TW],
+                                    vv[4 * IT_CH * IT_TW], a.eps);
+            a.fout[(size_t)oy * a.fout_pitch + x] = d;
+            if (a.m2) a.m2[(size_t)oy * a.m2_pitch + x] = d.x * d.x + d.y * d.y;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename TS, int R, int PRIOR>
+__global__ __launch_bounds__(IT_THREADS) void k_iter(IterArgs a, int32_t strip, int32_t nx, int32_t ntiles)
+{
+    using G = IterGeom<R>;
+    __shared__ float lds[G::GH + G::HN];
 
     // XCD-aware tile order: hardware hands workgroup b to XCD b % 8, so give
     // each XCD a contiguous run of tiles (neighbours share halo columns in L2)
@@ -332,75 +531,41 @@ __global__ __launch_bounds__(256) void k_iter(IterArgs a, int32_t strip, int32_t
     const int n8 = ntiles & ~7;
     if (b < n8) b = (b & 7) * (n8 >> 3) + (b >> 3);
     const int tx = b % nx, ty = b / nx;
-    const int x0 = tx * IT_TW;
-    const int ys = ty * strip, ye = min(ys + strip, a.h);
-    const TS *r1 = (const TS *)a.r1, *r2 = (const TS *)a.r2;
-    const int t = threadIdx.x;
-
-    for (int cy = ys - R; cy < ye + R; cy += IT_CH) {
-        // 1. per-pixel terms of rows [cy, cy + IT_CH)
-        for (int i = t; i < IT_CH * CW; i += 256) {
-            const int r = i / CW, c = i - r * CW;
-            const int y = clampi(cy + r, 0, a.h - 1), x = clampi(x0 - R + c, 0, a.w - 1);
-            float g[5];
-            update_terms<TS>(a, r1, r2, y, x, g);
+    IterCtx cx;
+    cx.x0 = tx * IT_TW;
+    cx.ys = ty * strip;
+    cx.ye = min(cx.ys + strip, a.h);
+    cx.y_first = cx.ys - R - G::PRE;
+    cx.nch = (cx.ye - cx.ys + IT_CH - 1) / IT_CH + G::J0;
+    const uint32_t npx = (uint32_t)a.h * a.rpitch;
+    IterRes rs;
+    rs.p4a = make_rsrc(a.p4[0], npx * Packed<TS>::B4);
+    rs.p1a = make_rsrc(a.p1[0], npx * Packed<TS>::B1);
+    rs.p4b = make_rsrc(a.p4[1], npx * Packed<TS>::B4);
+    rs.p1b = make_rsrc(a.p1[1], npx * Packed<TS>::B1);
+    rs.fin = make_rsrc(a.fin, PRIOR == PRIOR_UPSAMPLE ? (uint32_t)a.hc * a.fin_pitch * 8u
+                                                      : (uint32_t)a.h * a.fin_pitch * 8u);
+    // step-1 pixels of this thread (the same slots in every chunk)
+    int rr[G::NR1], cc[G::NR1], xs_[G::NR1];
+    bool live[G::NR1];
 #pragma unroll
-            for (int k = 0; k < 5; ++k) gh[k][r][c] = g[k];
-        }
-        __syncthreads();
-        // 2. horizontal sums: task = (channel, row, 16-column segment)
-        if (t < 5 * IT_CH * (IT_TW / IT_SEG)) {
-            const int k = t / (IT_CH * (IT_TW / IT_SEG));
-            const int rem = t - k * (IT_CH * (IT_TW / IT_SEG));
-            const int r = rem / (IT_TW / IT_SEG), sg = rem - r * (IT_TW / IT_SEG);
-            const float *src = &gh[k][r][sg * IT_SEG];
-            float v[IT_SEG + 2 * R];
+    for (int m = 0; m < G::NR1; ++m) {
+        const int i = (int)threadIdx.x + IT_THREADS * m;
+        live[m] = i < IT_CH * G::CW;
+        const int ic = live[m] ? i : 0;
+        rr[m] = ic / G::CW;
+        cc[m] = ic - rr[m] * G::CW;
+        xs_[m] = clampi(cx.x0 - R + cc[m], 0, a.w - 1);
+    }
+    float ring[G::RING];
 #pragma unroll
-            for (int j = 0; j < IT_SEG + 2 * R; ++j) v[j] = src[j];
-            float *dst = &hs[k][(cy + r - (ys - R)) % RING][sg * IT_SEG];
-#pragma unroll
-            for (int j = 0; j < IT_SEG; ++j) {
-                float sum = 0.f;
-#pragma unroll
-                for (int u = 0; u <= 2 * R; ++u) sum += v[j + u];
-                dst[j] = sum;
-            }
-        }
-        __syncthreads();
-        // 3. outputs [cy - R, cy - R + IT_CH) that lie in the strip; thread
-        //    (column c, pair q) finishes rows cy - R + 2q and cy - R + 2q + 1
-        {
-            const int c = t & (IT_TW - 1), q = t >> 6;
-            const int oy = cy - R + 2 * q, x = x0 + c;
-            if (oy + 1 >= ys && oy < ye && x < a.w) {
-                float S0[5], S1[5];
-#pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    float col[2 * R + 2];
-#pragma unroll
-                    for (int u = 0; u < 2 * R + 2; ++u) col[u] = hs[k][(oy - ys + u + RING) % RING][c];
-                    float s0 = 0.f, s1 = 0.f;
-#pragma unroll
-                    for (int u = 0; u <= 2 * R; ++u) {
-                        s0 += col[u];
-                        s1 += col[u + 1];
-                    }
-                    S0[k] = s0;
-                    S1[k] = s1;
-                }
-                if (oy >= ys) {
-                    const float2 d = solve2(S0[0], S0[1], S0[2], S0[3], S0[4], a.eps);
-                    a.fout[(size_t)oy * a.fout_pitch + x] = d;
-                    if (a.m2) a.m2[(size_t)oy * a.m2_pitch + x] = d.x * d.x + d.y * d.y;
-                }
-                if (oy + 1 < ye) {
-                    const float2 d = solve2(S1[0], S1[1], S1[2], S1[3], S1[4], a.eps);
-                    a.fout[(size_t)(oy + 1) * a.fout_pitch + x] = d;
-                    if (a.m2) a.m2[(size_t)(oy + 1) * a.m2_pitch + x] = d.x * d.x + d.y * d.y;
-                }
-            }
-        }
-        __syncthreads();
+    for (int i = 0; i < G::RING; ++i) ring[i] = 0.f;
+    for (int j = 0; j < cx.nch; j += G::NPH) {
+        iter_chunk<TS, R, PRIOR, 0>(a, rs, lds, cx, j, rr, cc, live, xs_, ring);
+        if (G::NPH > 1 && j + 1 < cx.nch)
+            iter_chunk<TS, R, PRIOR, 1 % G::NPH>(a, rs, lds, cx, j + 1, rr, cc, live, xs_, ring);
+        if (G::NPH > 2 && j + 2 < cx.nch)
+            iter_chunk<TS, R, PRIOR, 2 % G::NPH>(a, rs, lds, cx, j + 2, rr, cc, live, xs_, ring);
     }
 }
 
