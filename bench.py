@@ -99,6 +99,8 @@ def main():
     value = npairs * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
+    from paper_2511_14419_amd import profiling
+    tr = profiling.load_traffic(os.path.join(ROOT, "profiles", "k_iter_traffic_plain_2048_u16.txt"))
     log("plain: %.1f pairs/s, %.2f ms/step; iteration kernel %.1f GB/s over %d launches"
         % (value, ms_per_step, achieved, k_n))
 
@@ -138,7 +140,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": tr["hbm_bytes_per_launch"] if tr else None,
+            "traffic_over_algorithmic": tr["hbm_over_algorithmic"] if tr else None,
             "launches": k_n,
             "avg_launch_us": round(1e3 * k_ms / max(k_n, 1), 3),
             "bytes_per_launch": round(k_bytes / max(k_n, 1)),

@@ -6,6 +6,7 @@ touches no pixel whose oracle magnitude lies within the tolerance of the
 threshold (the band rule; dilation is monotone, so outside the band the
 threshold decision and hence the mask are fixed).
 """
+import os
 import sys
 
 import numpy as np
@@ -27,6 +28,10 @@ def F():
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+    rep = os.environ.get("FLOWROI_REPORT")
+    if rep:
+        with open(rep, "a") as fh:
+            fh.write(" ".join(str(x) for x in a) + "\n")
 
 
 def run_gpu(prev, nxt, dev, **kw):
