@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--frames", type=int, default=N_FRAMES)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline path only")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-streams", type=int, default=64)
+    ap.add_argument("--serve-rates", type=str, default="8,256,1024,1536,2048,2560,3072")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the frame streams "
@@ -152,6 +155,10 @@ def main():
         out["streaming"] = bench_streaming(fl, frames, p, dev, args)
         out["batched"] = bench_batched(fl, dev, args, fp16=False)
         out["batched_fp16"] = bench_batched(fl, dev, args, fp16=True)
+        if not args.no_serving:
+            del flows, masks
+            torch.cuda.empty_cache()
+            out["serving"] = bench_serving(fl, dev, args)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(seq)
@@ -210,6 +217,77 @@ def bench_batched(fl, dev, args, fp16):
          "frames_2048_equiv_per_s": round(px / dt / (H * W), 2), "storage": "f16" if fp16 else "f32"}
     log("batched %s: %s" % (r["storage"], r))
     return r
+
+
+def bench_serving(fl, dev, args):
+    """64 lens streams (384-well mode) of 2048x2048 u16 frames arriving as a
+    Poisson process at each aggregate rate; latency is arrival in host
+    memory -> mask ready on the device."""
+    import numpy as np
+    import torch
+
+    from paper_2511_14419_amd import synth
+    ns = args.serve_streams
+    nseq, nfr = 8, 4
+    seqs = [synth.sequence_u16(H, W, nfr, 200, 500 + i) for i in range(nseq)]
+    host = [[torch.from_numpy(q[t]).pin_memory() for t in range(nfr)] for q in seqs]
+    cfg = fl.server_config(H, W, fl.ROI_U16, hbm_budget=96 << 30, max_streams=ns, max_batch=ns, max_inflight=2,
+                           queue_depth=16)
+    srv = fl.Server(cfg)
+    ids = []
+    for _ in range(ns):
+        sid = srv.open_stream()
+        if sid is None:
+            break
+        ids.append(sid)
+    outs = [[(torch.empty((H, W, 2), device=dev), torch.empty((H, W), dtype=torch.uint8, device=dev))
+             for _ in range(2)] for _ in ids]
+    cyc = [0] * len(ids)
+    nsub = [0] * len(ids)
+
+    def next_frame(k):
+        # palindromic cycle 0 1 2 3 2 1 0 1 ...
+        c = cyc[k] % (2 * nfr - 2)
+        cyc[k] += 1
+        return host[k % nseq][c if c < nfr else 2 * nfr - 2 - c]
+
+    for k, sid in enumerate(ids):  # prime every stream with its first frame
+        srv.submit(sid, next_frame(k), outs[k][0][0], outs[k][0][1])
+    srv.drain()
+    srv.poll(1 << 16)
+    rng = np.random.default_rng(7)
+    points = []
+    for rate in [float(r) for r in args.serve_rates.split(",")]:
+        n = int(min(max(rate * 2.0, 64), 4000))
+        gaps = rng.exponential(1.0 / rate, n)
+        who = rng.integers(0, len(ids), n)
+        t0 = fl.steady_now() + 0.01
+        t_next = t0
+        dropped = 0
+        for g, k in zip(gaps, who):
+            t_next += g
+            while fl.steady_now() < t_next:
+                pass
+            slot = outs[k][nsub[k] % 2]
+            if srv.submit(ids[k], next_frame(k), slot[0], slot[1], tag=int(k)):
+                nsub[k] += 1
+            else:
+                dropped += 1
+        srv.drain()
+        res = [r for r in srv.poll(1 << 16) if r["status"] == fl.ROI_OK]
+        lat = np.array([r["t_done"] - r["t_arrival"] for r in res]) * 1e3
+        span = max(r["t_done"] for r in res) - min(r["t_arrival"] for r in res)
+        pt = {"rate_fps": rate, "frames": len(res), "dropped": dropped, "frames_per_s": round(len(res) / span, 1),
+              "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+              "mean_batch": round(float(np.mean([r["batch"] for r in res])), 2)}
+        points.append(pt)
+        log("serving: %s" % pt)
+        if pt["p99_ms"] > 200 or dropped > n // 10:
+            break
+    srv.close()
+    best = max(points, key=lambda q: q["frames_per_s"])
+    return {"streams": len(ids), "stream_bytes": fl.Server.stream_bytes(cfg), "points": points,
+            "max_frames_per_s": best["frames_per_s"]}
 
 
 def cpu_baseline(seq):

@@ -181,6 +181,77 @@ roi_status roi_stream_push_many(int32_t n, void *const *ctxs, const void *const 
                                 const int64_t *pitches, float *const *flows, uint8_t *const *masks,
                                 int32_t *status, void *stream);
 
+/* ---- Serving: continuous batching over many camera streams -------------- */
+
+/* A server owns up to max_streams stream contexts of one frame size, dtype
+ * and parameter set. Frames are submitted from host memory as they arrive;
+ * a scheduler thread forms steps of at most one ready frame per stream
+ * (oldest arrival first, at most max_batch frames), copies them to the
+ * device on a copy stream and runs them on four compute streams (each
+ * server stream always on the same one, which keeps its frames in order).
+ * Up to max_inflight steps are on the GPU at once; frames that arrive
+ * while a step runs join a later step. A completion thread stamps each
+ * frame's completion time. Every result equals what roi_stream_push gives
+ * for that stream alone. */
+typedef struct roi_server_config {
+    int32_t h, w;
+    roi_dtype dtype;
+    roi_params params;
+    size_t hbm_budget;      /* device bytes the server may hold (stream state + staging) */
+    int32_t max_streams;    /* 1..256 */
+    int32_t max_batch;      /* frames per step, 1..256 */
+    int32_t max_inflight;   /* steps on the GPU at once, 1..4 */
+    int32_t queue_depth;    /* frames a stream may have queued, 1..64 */
+} roi_server_config;
+
+typedef struct roi_server_result {
+    uint64_t tag;           /* the caller's tag from roi_server_submit */
+    int32_t stream;         /* server stream id */
+    int32_t status;         /* ROI_OK, ROI_PRIMED (first frame), or an error */
+    double t_arrival;       /* seconds on the steady clock, at submit */
+    double t_done;          /* seconds, when the GPU finished the frame's step */
+    int32_t batch;          /* frames in the step that carried it */
+    int32_t pad;
+} roi_server_result;
+
+/* Validates the config and starts the threads; allocates nothing on the
+ * device until streams open. */
+roi_status roi_server_create(const roi_server_config *cfg, void **out_srv);
+
+/* Admission: opens a stream if its resident state fits in what is left of
+ * the HBM budget (ROI_ENOMEM otherwise: the caller may retry once another
+ * stream closes). Allocates the stream's context and two device frame
+ * slots. */
+roi_status roi_server_open_stream(void *srv, int32_t *out_id);
+
+/* Closes a stream after its queued frames complete; frees its memory. */
+roi_status roi_server_close_stream(void *srv, int32_t id);
+
+/* Device bytes one stream holds (context + frame slots). */
+size_t roi_server_stream_bytes(const roi_server_config *cfg);
+
+/* Queues one frame for stream `id`. host_frame (h rows, `pitch` elements
+ * per row) must stay valid and unchanged until the frame's result has been
+ * polled; pinned memory gives asynchronous copies. flow (h*w*2 floats) and
+ * mask (h*w uint8) are device buffers the caller owns; they are written
+ * when the frame completes (not for a ROI_PRIMED first frame). Returns
+ * ROI_EINVAL for a bad id or pointer and ROI_ENOMEM when the stream's
+ * queue is full (the frame is then not queued). The arrival time is taken
+ * here. */
+roi_status roi_server_submit(void *srv, int32_t id, const void *host_frame, int64_t pitch, float *flow,
+                             uint8_t *mask, uint64_t tag);
+
+/* Moves up to `max` completed results (in completion order) into `out`;
+ * returns how many. Non-blocking. */
+int32_t roi_server_poll(void *srv, roi_server_result *out, int32_t max);
+
+/* Blocks until every submitted frame has completed (or an error stops the
+ * server); ROI_OK or the first error seen. */
+roi_status roi_server_drain(void *srv);
+
+/* Stops the threads (after draining) and frees everything. */
+void roi_server_destroy(void *srv);
+
 /* ---- Kernel timing ------------------------------------------------------ */
 
 /* When enabled, the library records HIP events around every launch of the

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libflowroi.so")
 SOURCES = [os.path.join(CSRC, "flowroi.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, "kernels.h"), os.path.join(INCLUDE, "flowroi.h")]
+DEPS = SOURCES + [os.path.join(CSRC, "kernels.h"), os.path.join(CSRC, "server.h"), os.path.join(INCLUDE, "flowroi.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are switched off for all device code.

@@ -994,3 +994,5 @@ const char *roi_status_str(roi_status s)
 }
 
 } // extern "C"
+
+#include "server.h"

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import time
 
 import torch
 
@@ -27,6 +28,8 @@ EXPORTED = [
     "roi_stream_create", "roi_stream_push", "roi_stream_reset", "roi_stream_state_bytes",
     "roi_stream_destroy", "roi_stream_push_many", "roi_timing_enable", "roi_timing_read",
     "roi_timing_reset", "roi_autotune", "roi_set_strip", "roi_tuned_strip", "roi_status_str",
+    "roi_server_create", "roi_server_open_stream", "roi_server_close_stream", "roi_server_stream_bytes",
+    "roi_server_submit", "roi_server_poll", "roi_server_drain", "roi_server_destroy",
 ]
 
 
@@ -44,6 +47,18 @@ class RoiParams(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RoiServerConfig(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_int32), ("w", ctypes.c_int32), ("dtype", ctypes.c_int32), ("params", RoiParams),
+                ("hbm_budget", ctypes.c_size_t), ("max_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("queue_depth", ctypes.c_int32)]
+
+
+class RoiServerResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("stream", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("t_arrival", ctypes.c_double), ("t_done", ctypes.c_double), ("batch", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class RoiPair(ctypes.Structure):
@@ -106,6 +121,23 @@ def lib():
         L.roi_set_strip.restype = i32
         L.roi_tuned_strip.argtypes = [i32, i32, i32, i32]
         L.roi_tuned_strip.restype = i32
+        sp = ctypes.POINTER(RoiServerConfig)
+        L.roi_server_create.argtypes = [sp, ctypes.POINTER(vp)]
+        L.roi_server_create.restype = i32
+        L.roi_server_open_stream.argtypes = [vp, ctypes.POINTER(i32)]
+        L.roi_server_open_stream.restype = i32
+        L.roi_server_close_stream.argtypes = [vp, i32]
+        L.roi_server_close_stream.restype = i32
+        L.roi_server_stream_bytes.argtypes = [sp]
+        L.roi_server_stream_bytes.restype = sz
+        L.roi_server_submit.argtypes = [vp, i32, vp, i64, vp, vp, ctypes.c_uint64]
+        L.roi_server_submit.restype = i32
+        L.roi_server_poll.argtypes = [vp, ctypes.POINTER(RoiServerResult), i32]
+        L.roi_server_poll.restype = i32
+        L.roi_server_drain.argtypes = [vp]
+        L.roi_server_drain.restype = i32
+        L.roi_server_destroy.argtypes = [vp]
+        L.roi_server_destroy.restype = None
         L.roi_status_str.argtypes = [i32]
         L.roi_status_str.restype = ctypes.c_char_p
         _lib = L
@@ -315,3 +347,75 @@ def set_strip(strip):
 
 def tuned_strip(h, w, winsize=15, fp16=False):
     return lib().roi_tuned_strip(h, w, winsize, 1 if fp16 else 0)
+
+
+def server_config(h, w, dtype, params=None, hbm_budget=1 << 36, max_streams=64, max_batch=64, max_inflight=2,
+                  queue_depth=8):
+    return RoiServerConfig(h, w, dtype, params or default_params(), hbm_budget, max_streams, max_batch,
+                           max_inflight, queue_depth)
+
+
+class Server:
+    """Continuous-batching server over camera streams (roi_server_* in the C ABI)."""
+
+    def __init__(self, cfg):
+        self.cfg = cfg
+        srv = ctypes.c_void_p()
+        _check(lib().roi_server_create(ctypes.byref(cfg), ctypes.byref(srv)), "roi_server_create")
+        self.srv = srv
+
+    @staticmethod
+    def stream_bytes(cfg):
+        return lib().roi_server_stream_bytes(ctypes.byref(cfg))
+
+    def open_stream(self):
+        """Stream id, or None when the HBM budget is exhausted."""
+        i = ctypes.c_int32(-1)
+        st = lib().roi_server_open_stream(self.srv, ctypes.byref(i))
+        if st == ROI_ENOMEM:
+            return None
+        _check(st, "roi_server_open_stream")
+        return i.value
+
+    def close_stream(self, sid):
+        _check(lib().roi_server_close_stream(self.srv, sid), "roi_server_close_stream")
+
+    def submit(self, sid, host_frame, flow, mask, tag=0):
+        """host_frame: pinned torch CPU tensor or numpy array (kept alive by the
+        caller until its result is polled). Returns False when the stream's
+        queue is full."""
+        if hasattr(host_frame, "data_ptr"):
+            ptr, pitch = host_frame.data_ptr(), host_frame.stride(0)
+        else:
+            ptr, pitch = host_frame.ctypes.data, host_frame.strides[0] // host_frame.itemsize
+        st = lib().roi_server_submit(self.srv, sid, ctypes.c_void_p(ptr), pitch, ctypes.c_void_p(flow.data_ptr()),
+                                     ctypes.c_void_p(mask.data_ptr() if mask is not None else 0), tag)
+        if st == ROI_ENOMEM:
+            return False
+        _check(st, "roi_server_submit")
+        return True
+
+    def poll(self, max_results=1024):
+        buf = (RoiServerResult * max_results)()
+        n = lib().roi_server_poll(self.srv, buf, max_results)
+        return [{"tag": buf[i].tag, "stream": buf[i].stream, "status": buf[i].status,
+                 "t_arrival": buf[i].t_arrival, "t_done": buf[i].t_done, "batch": buf[i].batch} for i in range(n)]
+
+    def drain(self):
+        _check(lib().roi_server_drain(self.srv), "roi_server_drain")
+
+    def close(self):
+        if self.srv:
+            lib().roi_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def steady_now():
+    """Seconds on the same steady clock as the server's time stamps."""
+    return time.monotonic()

@@ -18,7 +18,7 @@ import os
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(PKG, "csrc", "kernels.h"), os.path.join(PKG, "csrc", "flowroi.hip")]
+KERNEL_SOURCES = [os.path.join(PKG, "csrc", "kernels.h")]
 COPY_BYTES = 256 << 20
 
 

@@ -130,3 +130,19 @@ def test_status_strings(F):
     for s in (0, 1, -1, -2, -3, -4):
         assert F.status_str(s)
     assert F.status_str(99) == "unknown status"
+
+
+def test_server_config_rejected_before_any_device_work(F):
+    L = F.lib()
+    srv = ctypes.c_void_p()
+    bad = F.server_config(64, 64, F.ROI_U8, max_streams=0)
+    assert L.roi_server_create(ctypes.byref(bad), ctypes.byref(srv)) == F.ROI_EINVAL
+    bad = F.server_config(64, 64, F.ROI_U8, max_inflight=9)
+    assert L.roi_server_create(ctypes.byref(bad), ctypes.byref(srv)) == F.ROI_EINVAL
+    bad = F.server_config(64, 64, F.ROI_U8, params=F.default_params(winsize=2))
+    assert L.roi_server_create(ctypes.byref(bad), ctypes.byref(srv)) == F.ROI_EINVAL
+    good = F.server_config(2048, 2048, F.ROI_U16)
+    per = L.roi_server_stream_bytes(ctypes.byref(good))
+    assert per > L.roi_stream_state_bytes(2048, 2048, 1, ctypes.byref(good.params))
+    assert L.roi_server_poll(None, None, 4) == 0
+    assert L.roi_server_submit(None, 0, None, 64, None, None, 0) == F.ROI_EINVAL
