@@ -443,22 +443,25 @@ template <typename TS, int R, int PRIOR, int P>
 __device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs, float *lds, const IterCtx &cx, int j,
                                            const int (&rr)[IterGeom<R>::NR1], const int (&cc)[IterGeom<R>::NR1],
                                            const bool (&live)[IterGeom<R>::NR1], const int (&xs_)[IterGeom<R>::NR1],
-                                           float (&ring)[IterGeom<R>::RING])
+                                           float (&ring)[IterGeom<R>::RING], PxIn (&pre)[IterGeom<R>::NR1])
 {
     using G = IterGeom<R>;
     float *gh = lds;          // [5][IT_CH][CW]; after step 2 reused as vs [5][IT_CH][IT_TW]
     float *hn = lds + G::GH;  // [5][IT_CH][IT_HSP]
     const int t = threadIdx.x;
     const int cy = cx.y_first + IT_CH * j;
-    // 1. per-pixel terms of rows [cy, cy + IT_CH)
+    // 1. per-pixel terms of rows [cy, cy + IT_CH). The position-only loads
+    //    of this chunk were issued during the previous one (pre); the next
+    //    chunk's are issued here, before this chunk's gathers are used.
 #pragma unroll
     for (int m = 0; m < G::NR1; ++m) {
+        const PxIn cur = pre[m];
+        const int y = clampi(cy + rr[m], 0, a.h - 1);
+        const PxG g = issue_gather<TS, PRIOR>(a, rs, cur, y, xs_[m]);
+        if (j + 1 < cx.nch) pre[m] = load_in<TS, PRIOR>(a, rs, clampi(cy + IT_CH + rr[m], 0, a.h - 1), xs_[m]);
         if (live[m]) {
-            const int y = clampi(cy + rr[m], 0, a.h - 1);
-            const PxIn in = load_in<TS, PRIOR>(a, rs, y, xs_[m]);
-            const PxG g = issue_gather<TS, PRIOR>(a, rs, in, y, xs_[m]);
             float o[5];
-            update_terms(in, g, o);
+            update_terms(cur, g, o);
 #pragma unroll
             for (int k = 0; k < 5; ++k) gh[(k * IT_CH + rr[m]) * G::CW + cc[m]] = o[k];
         }
@@ -560,12 +563,15 @@ __global__ __launch_bounds__(IT_THREADS) void k_iter(IterArgs a, int32_t strip, 
     float ring[G::RING];
 #pragma unroll
     for (int i = 0; i < G::RING; ++i) ring[i] = 0.f;
+    PxIn pre[G::NR1];
+#pragma unroll
+    for (int m = 0; m < G::NR1; ++m) pre[m] = load_in<TS, PRIOR>(a, rs, clampi(cx.y_first + rr[m], 0, a.h - 1), xs_[m]);
     for (int j = 0; j < cx.nch; j += G::NPH) {
-        iter_chunk<TS, R, PRIOR, 0>(a, rs, lds, cx, j, rr, cc, live, xs_, ring);
+        iter_chunk<TS, R, PRIOR, 0>(a, rs, lds, cx, j, rr, cc, live, xs_, ring, pre);
         if (G::NPH > 1 && j + 1 < cx.nch)
-            iter_chunk<TS, R, PRIOR, 1 % G::NPH>(a, rs, lds, cx, j + 1, rr, cc, live, xs_, ring);
+            iter_chunk<TS, R, PRIOR, 1 % G::NPH>(a, rs, lds, cx, j + 1, rr, cc, live, xs_, ring, pre);
         if (G::NPH > 2 && j + 2 < cx.nch)
-            iter_chunk<TS, R, PRIOR, 2 % G::NPH>(a, rs, lds, cx, j + 2, rr, cc, live, xs_, ring);
+            iter_chunk<TS, R, PRIOR, 2 % G::NPH>(a, rs, lds, cx, j + 2, rr, cc, live, xs_, ring, pre);
     }
 }
 
