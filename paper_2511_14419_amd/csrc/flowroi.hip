@@ -83,12 +83,15 @@ Plan make_plan(int h, int w, const roi_params *p)
         Level &v = pl.lv[l];
         v.h = level_dim(h, l);
         v.w = level_dim(w, l);
-        v.pitch = (int)align_up((size_t)v.w, 64);
+        // at least one padding column: the iteration kernel's (x0 + 1) corner
+        // at the right edge reads it (zero weight, zeroed by the expansion)
+        v.pitch = (int)align_up((size_t)v.w + 1, 64);
         const size_t plane = (size_t)v.h * v.pitch;
+        const size_t pplane = (size_t)(v.h + 1) * v.pitch; // packed planes: one zero row below the frame
         for (int f = 0; f < 2; ++f) {
             v.img[f] = l > 0 ? take(plane * pl.is) : 0;
-            v.r4[f] = take(4 * plane * pl.ts);
-            v.r1[f] = take(plane * pl.ts);
+            v.r4[f] = take(4 * pplane * pl.ts);
+            v.r1[f] = take(pplane * pl.ts);
         }
         v.fa = take(plane * sizeof(float2));
         v.fb = l > 0 ? take(plane * sizeof(float2)) : 0;
@@ -204,7 +207,9 @@ void launch_pyr(const PyrArgs &a, int frames, hipStream_t s)
 template <typename TIn, typename TOut>
 void launch_poly(const PolyArgs &a, int frames, hipStream_t s)
 {
-    dim3 g((a.w + PE_TW - 1) / PE_TW, (a.h + PE_TH - 1) / PE_TH, frames);
+    // packed output also covers the zero padding columns and the zero row below the frame
+    const int cols = a.packed ? a.dpitch : a.w;
+    dim3 g((cols + PE_TW - 1) / PE_TW, (a.h + (a.packed ? 1 : 0) + PE_TH - 1) / PE_TH, frames);
     hipLaunchKernelGGL((k_polyexp<TIn, TOut>), g, dim3(256), 0, s, a);
 }
 
@@ -623,7 +628,7 @@ roi_status roi_validate(int32_t h, int32_t w, roi_dtype dtype, const roi_params 
     if (h > 32768 || w > 32768) return ROI_EUNSUPPORTED;
     // the iteration kernel addresses a level's packed plane (16 B per pixel
     // of a 64-aligned row) with 32-bit byte offsets
-    if ((uint64_t)h * align_up((size_t)w, 64) * 16 >= (1ull << 32)) return ROI_EUNSUPPORTED;
+    if ((uint64_t)(h + 1) * align_up((size_t)w + 1, 64) * 16 >= (1ull << 32)) return ROI_EUNSUPPORTED;
     return ROI_OK;
 }
 

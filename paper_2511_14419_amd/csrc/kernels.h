@@ -51,36 +51,40 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint3
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
 }
 
-__device__ __forceinline__ float4 bload4(__amdgpu_buffer_rsrc_t r, uint32_t off)
+__device__ __forceinline__ float4 bload4(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0)
 {
-    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, 0));
 }
 __device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t off)
 {
     return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
-__device__ __forceinline__ float bload1(__amdgpu_buffer_rsrc_t r, uint32_t off)
+__device__ __forceinline__ float bload1(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
 }
-__device__ __forceinline__ float bload1h(__amdgpu_buffer_rsrc_t r, uint32_t off)
+__device__ __forceinline__ float bload1h(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0)
 {
-    return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)));
+    return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0)));
 }
-__device__ __forceinline__ float4 bload4h(__amdgpu_buffer_rsrc_t r, uint32_t off)
+__device__ __forceinline__ float4 bload4h(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0)
 {
-    const uint2 u = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    const uint2 u = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
     const __half2 lo = __builtin_bit_cast(__half2, u.x), hi = __builtin_bit_cast(__half2, u.y);
     return make_float4(__low2float(lo), __high2float(lo), __low2float(hi), __high2float(hi));
 }
 
 // Packed storage of one frame's expansion: P4 = (b_x, b_y, A_xx, A_yy) per
-// pixel (float4, or 4 x FP16), P1 = A_xy (float or FP16). Both h x pitch.
+// pixel (float4, or 4 x FP16), P1 = A_xy (float or FP16). Both (h + 1) x
+// pitch: columns w..pitch-1 and row h are zero.
 template <typename TS> struct Packed;
 template <> struct Packed<float> {
     static constexpr uint32_t B4 = 16, B1 = 4;
     __device__ static float4 load4(__amdgpu_buffer_rsrc_t r, uint32_t px) { return bload4(r, px * B4); }
     __device__ static float load1(__amdgpu_buffer_rsrc_t r, uint32_t px) { return bload1(r, px * B1); }
+    // byte offset + scalar offset (row stride) forms, for the bilinear corners
+    __device__ static float4 load4b(__amdgpu_buffer_rsrc_t r, uint32_t b, uint32_t sb) { return bload4(r, b, sb); }
+    __device__ static float load1b(__amdgpu_buffer_rsrc_t r, uint32_t b, uint32_t sb) { return bload1(r, b, sb); }
     __device__ static void store(void *p4, void *p1, size_t px, const float o[5])
     {
         ((float4 *)p4)[px] = make_float4(o[0], o[1], o[2], o[3]);
@@ -91,6 +95,8 @@ template <> struct Packed<__half> {
     static constexpr uint32_t B4 = 8, B1 = 2;
     __device__ static float4 load4(__amdgpu_buffer_rsrc_t r, uint32_t px) { return bload4h(r, px * B4); }
     __device__ static float load1(__amdgpu_buffer_rsrc_t r, uint32_t px) { return bload1h(r, px * B1); }
+    __device__ static float4 load4b(__amdgpu_buffer_rsrc_t r, uint32_t b, uint32_t sb) { return bload4h(r, b, sb); }
+    __device__ static float load1b(__amdgpu_buffer_rsrc_t r, uint32_t b, uint32_t sb) { return bload1h(r, b, sb); }
     __device__ static void store(void *p4, void *p1, size_t px, const float o[5])
     {
         const __half2 lo = __floats2half2_rn(o[0], o[1]), hi = __floats2half2_rn(o[2], o[3]);
@@ -219,7 +225,17 @@ __global__ __launch_bounds__(256) void k_polyexp(PolyArgs a)
     for (int i = threadIdx.x; i < PE_TH * PE_TW; i += 256) {
         const int r = i / PE_TW, c = i - r * PE_TW;
         const int y = oy0 + r, x = ox0 + c;
-        if (y >= a.h || x >= a.w) continue;
+        if (y > a.h || (y == a.h && !a.packed)) continue;
+        if (x >= a.w || y == a.h) {
+            // packed planes: zero the row padding and the extra row below the
+            // frame (the iteration kernel's bilinear corners may read them
+            // with zero weight)
+            if (a.packed && x < a.dpitch) {
+                const float z[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+                Packed<TOut>::store(a.dst[blockIdx.z], a.dst1[blockIdx.z], (size_t)y * a.dpitch + x, z);
+            }
+            continue;
+        }
         double bx = 0.0, by = 0.0, axy = 0.0, axx = 0.0, ayy = 0.0;
         for (int t = 0; t <= 2 * n; ++t) {
             const double v0 = vr[0][r][c + t], v1 = vr[1][r][c + t], v2 = vr[2][r][c + t];
@@ -347,34 +363,38 @@ __device__ __forceinline__ float2 prior_of(const IterArgs &a, const PxIn &in, in
 // the real-valued point (outside -> edge pixel, zero weight). A NaN prior
 // clamps to the frame's left/top edge, so every load stays in bounds.
 template <typename TS, int PRIOR>
-__device__ __forceinline__ PxG issue_gather(const IterArgs &a, const IterRes &rs, const PxIn &in, int y, int x)
+__device__ __forceinline__ PxG issue_gather(const IterArgs &a, const IterRes &rs, const PxIn &in, int y, int x,
+                                            float xlo, float xhi)
 {
     using PK = Packed<TS>;
     PxG g;
     g.d = prior_of<PRIOR>(a, in, y, x);
     // clamping x + d~ into [0, w-1] is clamping d~ into [-x, w-1-x] (integer
     // bounds: exact); afterwards x0 = w-1 implies a zero fraction
-    const float dxc = fminf(fmaxf(g.d.x, (float)-x), (float)(a.w - 1 - x));
+    const float dxc = fminf(fmaxf(g.d.x, xlo), xhi);
     const float dyc = fminf(fmaxf(g.d.y, (float)-y), (float)(a.h - 1 - y));
     const float flx = floorf(dxc), fly = floorf(dyc);
     g.fx = dxc - flx;
     g.fy = dyc - fly;
-    const int x0 = x + (int)flx, y0 = y + (int)fly;
-    const uint32_t dxi = x0 < a.w - 1 ? 1u : 0u, dyi = y0 < a.h - 1 ? (uint32_t)a.rpitch : 0u;
-    const uint32_t c00 = (uint32_t)y0 * a.rpitch + x0;
-    g.v00 = PK::load4(rs.p4b, c00);
-    g.v01 = PK::load4(rs.p4b, c00 + dxi);
-    g.v10 = PK::load4(rs.p4b, c00 + dyi);
-    g.v11 = PK::load4(rs.p4b, c00 + dyi + dxi);
-    g.w00 = PK::load1(rs.p1b, c00);
-    g.w01 = PK::load1(rs.p1b, c00 + dxi);
-    g.w10 = PK::load1(rs.p1b, c00 + dyi);
-    g.w11 = PK::load1(rs.p1b, c00 + dyi + dxi);
+    const uint32_t c00 = (uint32_t)(y + (int)fly) * a.rpitch + (uint32_t)(x + (int)flx);
+    // corners (x0+1, y0+1) at +1 pixel / +1 row; at the right or bottom edge
+    // they have zero weight and read the zeroed row padding, the next row's
+    // first pixel or (past the last row) the descriptor's out-of-range zero
+    const uint32_t row4 = (uint32_t)a.rpitch * PK::B4, row1 = (uint32_t)a.rpitch * PK::B1;
+    const uint32_t o4 = c00 * PK::B4, o1 = c00 * PK::B1;
+    g.v00 = PK::load4b(rs.p4b, o4, 0);
+    g.v01 = PK::load4b(rs.p4b, o4 + PK::B4, 0);
+    g.v10 = PK::load4b(rs.p4b, o4, row4);
+    g.v11 = PK::load4b(rs.p4b, o4 + PK::B4, row4);
+    g.w00 = PK::load1b(rs.p1b, o1, 0);
+    g.w01 = PK::load1b(rs.p1b, o1 + PK::B1, 0);
+    g.w10 = PK::load1b(rs.p1b, o1, row1);
+    g.w11 = PK::load1b(rs.p1b, o1 + PK::B1, row1);
     return g;
 }
 
 // Per-pixel normal-equation terms G = A^T A (g11, g12, g22) and h = A^T db
-// for the prior displacement d~:
+// for the prior displacement d~, computed as 4 G and 4 h:
 //   A  = (A1(x) + A2(x + d~)) / 2,  db = -(b2(x + d~) - b1(x)) / 2 + A d~.
 __device__ __forceinline__ void update_terms(const PxIn &in, const PxG &g, float o[5])
 {
@@ -383,14 +403,16 @@ __device__ __forceinline__ void update_terms(const PxIn &in, const PxG &g, float
     const float c11 = bilerp(g.v00.z, g.v01.z, g.v10.z, g.v11.z, g.fx, g.fy);
     const float c22 = bilerp(g.v00.w, g.v01.w, g.v10.w, g.v11.w, g.fx, g.fy);
     const float c12 = bilerp(g.w00, g.w01, g.w10, g.w11, g.fx, g.fy);
-    const float A11 = 0.5f * (in.q1.z + c11), A22 = 0.5f * (in.q1.w + c22), A12 = 0.5f * (in.a12 + c12);
-    const float dbx = -0.5f * (b2x - in.q1.x) + A11 * g.d.x + A12 * g.d.y;
-    const float dby = -0.5f * (b2y - in.q1.y) + A12 * g.d.x + A22 * g.d.y;
-    o[0] = A11 * A11 + A12 * A12;
-    o[1] = A12 * (A11 + A22);
-    o[2] = A12 * A12 + A22 * A22;
-    o[3] = A11 * dbx + A12 * dby;
-    o[4] = A12 * dbx + A22 * dby;
+    // 2A and 2 db: every term below is 4x the plain one (an exact power-of-two
+    // scale), which the scale-free solve leaves unchanged bit for bit
+    const float S11 = in.q1.z + c11, S22 = in.q1.w + c22, S12 = in.a12 + c12;
+    const float ex = -(b2x - in.q1.x) + S11 * g.d.x + S12 * g.d.y;
+    const float ey = -(b2y - in.q1.y) + S12 * g.d.x + S22 * g.d.y;
+    o[0] = S11 * S11 + S12 * S12;
+    o[1] = S12 * (S11 + S22);
+    o[2] = S12 * S12 + S22 * S22;
+    o[3] = S11 * ex + S12 * ey;
+    o[4] = S12 * ex + S22 * ey;
 }
 
 // Solve of the pooled 2x2 system G d = h (g11, g12, g22, h1, h2):
@@ -413,7 +435,8 @@ __device__ __forceinline__ float2 solve2(float g11, float g12, float g22, float 
 //   3a. thread (channel, column) appends its 8 new horizontal sums to a
 //      register ring and forms the vertical sums of one aligned group of 8
 //      output rows -> LDS;
-//   3b. the 2x2 solves of those 512 pixels.
+//   3b. the 2x2 solves of those 512 pixels (no barrier after it: the next
+//      chunk's loads start while slower waves still solve).
 // Computed rows start PRE rows above ys - R so that output groups sit at
 // multiples of 8; every window sum is either taken directly (first of an
 // 8-column segment / 8-row group) or slid by one from its neighbour, in a
@@ -430,8 +453,9 @@ template <int R> struct IterGeom {
     static constexpr int NPH = J0 + 1;                            // ring phases
     static constexpr int RING = IT_CH * NPH;                      // ring length (>= IT_CH + 2R)
     static constexpr int NR1 = (IT_CH * CW + IT_THREADS - 1) / IT_THREADS; // step-1 pixels per thread
-    static constexpr int GH = 5 * IT_CH * CW;                     // floats of step-1 terms (reused by 3a)
+    static constexpr int GH = 5 * IT_CH * CW;                     // floats of step-1 terms
     static constexpr int HN = 5 * IT_CH * IT_HSP;                 // floats of new horizontal sums
+    static constexpr int VS = 5 * IT_CH * IT_TW;                  // floats of vertical sums
 };
 
 struct IterCtx {
@@ -446,8 +470,9 @@ __device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs,
                                            float (&ring)[IterGeom<R>::RING], PxIn (&pre)[IterGeom<R>::NR1])
 {
     using G = IterGeom<R>;
-    float *gh = lds;          // [5][IT_CH][CW]; after step 2 reused as vs [5][IT_CH][IT_TW]
-    float *hn = lds + G::GH;  // [5][IT_CH][IT_HSP]
+    float *gh = lds;                  // [5][IT_CH][CW]
+    float *hn = lds + G::GH;          // [5][IT_CH][IT_HSP]
+    float *vsb = lds + G::GH + G::HN; // [5][IT_CH][IT_TW]
     const int t = threadIdx.x;
     const int cy = cx.y_first + IT_CH * j;
     // 1. per-pixel terms of rows [cy, cy + IT_CH). The position-only loads
@@ -456,8 +481,8 @@ __device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs,
 #pragma unroll
     for (int m = 0; m < G::NR1; ++m) {
         const PxIn cur = pre[m];
-        const int y = clampi(cy + rr[m], 0, a.h - 1);
-        const PxG g = issue_gather<TS, PRIOR>(a, rs, cur, y, xs_[m]);
+        const PxG g = issue_gather<TS, PRIOR>(a, rs, cur, clampi(cy + rr[m], 0, a.h - 1), xs_[m], -(float)xs_[m],
+                                              (float)(a.w - 1 - xs_[m]));
         if (j + 1 < cx.nch) pre[m] = load_in<TS, PRIOR>(a, rs, clampi(cy + IT_CH + rr[m], 0, a.h - 1), xs_[m]);
         if (live[m]) {
             float o[5];
@@ -498,7 +523,7 @@ __device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs,
         float sum = 0.f;
 #pragma unroll
         for (int u = 0; u <= 2 * R; ++u) sum += ring[(S0 + u) % G::RING];
-        float *vs = gh + k * IT_CH * IT_TW + c;
+        float *vs = vsb + k * IT_CH * IT_TW + c;
         vs[0] = sum;
 #pragma unroll
         for (int i = 1; i < IT_CH; ++i) {
@@ -512,21 +537,21 @@ __device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs,
         const int i = px >> 6, cc2 = px & 63;
         const int oy = cx.ys + IT_CH * grp + i, x = cx.x0 + cc2;
         if (oy < cx.ye && x < a.w) {
-            const float *vv = gh + i * IT_TW + cc2;
+            const float *vv = vsb + i * IT_TW + cc2;
             const float2 d = solve2(vv[0], vv[IT_CH * IT_TW], vv[2 * IT_CH * IT_TW], vv[3 * IT_CH * IT_TW],
                                     vv[4 * IT_CH * IT_TW], a.eps);
             a.fout[(size_t)oy * a.fout_pitch + x] = d;
             if (a.m2) a.m2[(size_t)oy * a.m2_pitch + x] = d.x * d.x + d.y * d.y;
         }
     }
-    __syncthreads();
+    // no barrier: vs is next written by 3a of a later chunk, two barriers away
 }
 
 template <typename TS, int R, int PRIOR>
 __global__ __launch_bounds__(IT_THREADS) void k_iter(IterArgs a, int32_t strip, int32_t nx, int32_t ntiles)
 {
     using G = IterGeom<R>;
-    __shared__ float lds[G::GH + G::HN];
+    __shared__ float lds[G::GH + G::HN + G::VS];
 
     // XCD-aware tile order: hardware hands workgroup b to XCD b % 8, so give
     // each XCD a contiguous run of tiles (neighbours share halo columns in L2)
@@ -540,7 +565,7 @@ __global__ __launch_bounds__(IT_THREADS) void k_iter(IterArgs a, int32_t strip, 
     cx.ye = min(cx.ys + strip, a.h);
     cx.y_first = cx.ys - R - G::PRE;
     cx.nch = (cx.ye - cx.ys + IT_CH - 1) / IT_CH + G::J0;
-    const uint32_t npx = (uint32_t)a.h * a.rpitch;
+    const uint32_t npx = (uint32_t)(a.h + 1) * a.rpitch; // packed planes carry one zero row below the frame
     IterRes rs;
     rs.p4a = make_rsrc(a.p4[0], npx * Packed<TS>::B4);
     rs.p1a = make_rsrc(a.p1[0], npx * Packed<TS>::B1);
