@@ -215,8 +215,33 @@ def bench_batched(fl, dev, args, fp16):
     px = sum(x.numel() for x in prevs)
     r = {"pairs": len(prevs), "ms_per_launch": round(dt * 1e3, 3), "mpx_per_s": round(px / dt / 1e6, 1),
          "frames_2048_equiv_per_s": round(px / dt / (H * W), 2), "storage": "f16" if fp16 else "f32"}
+    if fp16 and not args.no_cpu_baseline:
+        r["error_vs_oracle"] = fp16_error(seqs, flows, masks)
     log("batched %s: %s" % (r["storage"], r))
     return r
+
+
+def fp16_error(seqs, flows, masks, delta=1e-3):
+    """Flow error of the FP16-storage results against the FP64 oracle over
+    every pixel of every pair, and the fraction of mask pixels that differ
+    where the structuring element touches no threshold-band pixel."""
+    import numpy as np
+
+    import oracle
+    emax, esum, n, flips, checked = 0.0, 0.0, 0, 0, 0
+    for q, f, m in zip(seqs, flows, masks):
+        ref_flow, ref_mask, t2 = oracle.roi_mask(q[0].astype(np.float64), q[1].astype(np.float64))
+        g = f.cpu().numpy().astype(np.float64)
+        e = np.abs(g - ref_flow)
+        emax = max(emax, float(e.max()))
+        esum += float(e.sum())
+        n += e.size
+        band = (np.abs(np.hypot(ref_flow[..., 0], ref_flow[..., 1]) - np.sqrt(t2)) <= delta).astype(np.uint8)
+        free = oracle.dilate(band, 2, 0) == 0
+        flips += int(((m.cpu().numpy() != ref_mask) & free).sum())
+        checked += int(free.sum())
+    return {"max_dflow_px": round(emax, 5), "mean_dflow_px": round(esum / n, 6),
+            "mask_flip_rate_outside_band": round(flips / max(checked, 1), 6)}
 
 
 def bench_serving(fl, dev, args):

@@ -62,7 +62,8 @@ enum {
 
 enum {
     ROI_USE_INITIAL_FLOW = 1u, /* `flow` holds an initial flow on entry (see roi_mask) */
-    ROI_FP16_STORAGE = 2u      /* pyramid images and expansions stored as FP16; FP32 math */
+    ROI_FP16_STORAGE = 2u      /* per-level expansions (the planes every iteration reads) stored as FP16;
+                                  pyramid images stay FP64, all arithmetic FP32/FP64 as without it */
 };
 
 /* Parameters of the path. Farneback's constants are not given by the paper

@@ -58,7 +58,7 @@ struct Plan {
     int L;
     bool fp16;
     size_t ts;        // storage bytes per expansion value
-    size_t is;        // storage bytes per pyramid image value (FP64, or FP16)
+    size_t is;        // storage bytes per pyramid image value (FP64)
     Level lv[MAX_LEVELS];
     size_t init_off;  // coarsest-level initial flow
     size_t m2_off;    // |d|^2 at full resolution, pitch lv[0].pitch
@@ -72,7 +72,7 @@ Plan make_plan(int h, int w, const roi_params *p)
     pl.L = p->levels;
     pl.fp16 = (p->flags & ROI_FP16_STORAGE) != 0;
     pl.ts = pl.fp16 ? 2 : 4;
-    pl.is = pl.fp16 ? 2 : 8;
+    pl.is = 8; // pyramid images stay FP64 in both variants (under 2 % of the traffic)
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -248,13 +248,8 @@ roi_status enqueue_expand(const Plan &pl, uint8_t *base, int nf, const void *con
         a.w = src.w;
         a.h2 = dst.h;
         a.w2 = dst.w;
-        if (pl.fp16) {
-            if (l == 1) launch_pyr_raw<__half>(dt, a, nf, s);
-            else launch_pyr<__half, __half>(a, nf, s);
-        } else {
-            if (l == 1) launch_pyr_raw<double>(dt, a, nf, s);
-            else launch_pyr<double, double>(a, nf, s);
-        }
+        if (l == 1) launch_pyr_raw<double>(dt, a, nf, s);
+        else launch_pyr<double, double>(a, nf, s);
         LAUNCH_CHECK();
     }
     for (int l = 0; l < pl.L; ++l) {
@@ -275,7 +270,7 @@ roi_status enqueue_expand(const Plan &pl, uint8_t *base, int nf, const void *con
         a.w = v.w;
         if (pl.fp16) {
             if (l == 0) launch_poly_raw<__half>(dt, a, nf, s);
-            else launch_poly<__half, __half>(a, nf, s);
+            else launch_poly<double, __half>(a, nf, s);
         } else {
             if (l == 0) launch_poly_raw<float>(dt, a, nf, s);
             else launch_poly<double, float>(a, nf, s);

@@ -381,8 +381,9 @@ def test_push_many_matches_single_streams():
 
 
 def test_fp16_storage_error_reported():
-    """FP16 pyramid/expansion storage: error against the FP64 oracle is
-    reported; the bound asserted is loose (the variant trades accuracy)."""
+    """FP16 storage of the per-level expansions: the error against the FP64
+    oracle is reported; the asserted bounds are loose (the variant trades
+    accuracy for half the iteration traffic)."""
     dev = device()
     seq = synth.sequence_u16(512, 512, 2, 13, 31)
     flow, mask, _ = run_gpu(seq[0], seq[1], dev, flags=2)
@@ -395,4 +396,4 @@ def test_fp16_storage_error_reported():
     say("  fp16: max |dflow| %.3g, mean %.3g, pre-mask flips outside band %.4f %%"
         % (err.max(), err.mean(), 100 * flips.mean()))
     assert np.isfinite(flow).all()
-    assert err.mean() < 0.1
+    assert err.mean() < 2e-3 and err.max() < 0.1
