@@ -98,6 +98,13 @@ def main():
     t1 = time.perf_counter()
     fl.timing_enable(False)
     k_ms, k_n, k_px, k_bytes = fl.timing_read()
+    recs = fl.timing_records()
+    per_level = {}
+    for ms_, px_, b_ in recs:
+        e = per_level.setdefault(px_, [0.0, 0.0, 0])
+        e[0] += ms_
+        e[1] += b_
+        e[2] += 1
     elapsed = t1 - t0
     value = npairs * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
@@ -148,6 +155,10 @@ def main():
             "launches": k_n,
             "avg_launch_us": round(1e3 * k_ms / max(k_n, 1), 3),
             "bytes_per_launch": round(k_bytes / max(k_n, 1)),
+            "per_level": [{"pixels": px_, "launches": e[2], "avg_launch_us": round(1e3 * e[0] / e[2], 2),
+                           "achieved_gbs": round(e[1] / (e[0] * 1e-3) / 1e9, 1),
+                           "frac": round(e[1] / (e[0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                          for px_, e in sorted(per_level.items(), reverse=True)],
         },
     }
 

@@ -267,6 +267,11 @@ void roi_timing_enable(int32_t on);
 roi_status roi_timing_read(double *total_ms, int64_t *launches, int64_t *pixels, double *bytes);
 void roi_timing_reset(void);
 
+/* Per-launch records behind roi_timing_read (same synchronisation): fills
+ * up to `max` entries of kernel ms, output pixels and algorithmic bytes, in
+ * launch order, and returns the number of records available. */
+int32_t roi_timing_records(double *ms, int64_t *pixels, double *bytes, int32_t max);
+
 /* ---- Tuning -------------------------------------------------------------- */
 
 /* The iteration kernel walks strips of 64 columns; the strip height only

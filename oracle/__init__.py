@@ -73,6 +73,10 @@ def _load():
             lib.orc_roi_mask.argtypes = [_dp, _dp, i, i, i, i, i, i, d, d, _dp, i, d, i, i, _dp, _u8p, _dp]
             lib.orc_roi_mask.restype = i
             lib.orc_num_threads.restype = i
+            lib.orc_median.argtypes = [_dp, i, i, i, _dp]
+            lib.orc_bilateral.argtypes = [_dp, i, i, i, d, d, _dp]
+            lib.orc_denoise.argtypes = [_dp, i, i, i, i, d, d, _dp]
+            lib.orc_denoise.restype = i
             _lib = lib
     return _lib
 
@@ -190,10 +194,40 @@ def dilate(pre, radius=2, shape=0):
     return out
 
 
+def median(img, radius=1):
+    img = _f64(img)
+    h, w = img.shape
+    out = np.empty_like(img)
+    _load().orc_median(_ptr(img), h, w, int(radius), _ptr(out))
+    return out
+
+
+def bilateral(img, radius=2, sigma_space=1.5, sigma_range=20.0):
+    img = _f64(img)
+    h, w = img.shape
+    out = np.empty_like(img)
+    _load().orc_bilateral(_ptr(img), h, w, int(radius), float(sigma_space), float(sigma_range), _ptr(out))
+    return out
+
+
+def denoise(img, median_radius=1, bilateral_radius=2, sigma_space=1.5, sigma_range=20.0):
+    """Median then bilateral filter (FlowRoI's two-step denoising)."""
+    img = _f64(img)
+    h, w = img.shape
+    out = np.empty_like(img)
+    _check(_load().orc_denoise(_ptr(img), h, w, int(median_radius), int(bilateral_radius), float(sigma_space),
+                               float(sigma_range), _ptr(out)))
+    return out
+
+
 def roi_mask(prev, next, levels=3, winsize=15, iterations=3, poly_n=5, poly_sigma=1.1, eps=1e-3,
-             thresh_mode=0, thresh=1.0, dilate_radius=2, se_shape=0, init=None):
-    """Whole path: returns (flow (h, w, 2), mask (h, w) uint8 0/1, tau^2)."""
+             thresh_mode=0, thresh=1.0, dilate_radius=2, se_shape=0, init=None, denoise_params=None):
+    """Whole path: returns (flow (h, w, 2), mask (h, w) uint8 0/1, tau^2).
+    denoise_params (dict of denoise()'s keywords) applies the denoising
+    pre-stage to both frames first."""
     p, q = _f64(prev), _f64(next)
+    if denoise_params is not None:
+        p, q = denoise(p, **denoise_params), denoise(q, **denoise_params)
     h, w = p.shape
     fl = np.empty((h, w, 2))
     mask = np.empty((h, w), dtype=np.uint8)

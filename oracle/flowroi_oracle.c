@@ -484,6 +484,71 @@ int orc_dilate(const uint8_t *pre, int h, int w, int r, int shape, uint8_t *mask
 }
 
 /* ------------------------------------------------------------------------ */
+/* Denoising pre-stage (FlowRoI Method, Optical flow extraction: median then  */
+/* bilateral filtering before the flow)                                      */
+/* ------------------------------------------------------------------------ */
+
+static int cmp_asc(const void *a, const void *b)
+{
+    const double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Median over the (2 mr + 1)^2 square around each pixel, replicate border. */
+void orc_median(const double *img, int h, int w, int mr, double *out)
+{
+    const int side = 2 * mr + 1, n = side * side;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < h; ++i) {
+        double buf[81];
+        for (int j = 0; j < w; ++j) {
+            int k = 0;
+            for (int u = -mr; u <= mr; ++u)
+                for (int v = -mr; v <= mr; ++v) buf[k++] = img[(size_t)clampi(i + u, 0, h - 1) * w + clampi(j + v, 0, w - 1)];
+            qsort(buf, n, sizeof(double), cmp_asc);
+            out[(size_t)i * w + j] = buf[n / 2];
+        }
+    }
+}
+
+/* Bilateral filter over the (2 br + 1)^2 square, replicate border:
+ * out(p) = sum_q ws(q - p) wr(I(q) - I(p)) I(q) / sum_q ws wr with
+ * ws(t) = exp(-|t|^2 / (2 ss^2)) and wr(e) = exp(-e^2 / (2 sr^2)). */
+void orc_bilateral(const double *img, int h, int w, int br, double ss, double sr, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < h; ++i)
+        for (int j = 0; j < w; ++j) {
+            const double c = img[(size_t)i * w + j];
+            double num = 0.0, den = 0.0;
+            for (int u = -br; u <= br; ++u)
+                for (int v = -br; v <= br; ++v) {
+                    const double q = img[(size_t)clampi(i + u, 0, h - 1) * w + clampi(j + v, 0, w - 1)];
+                    const double wt = exp(-(double)(u * u + v * v) / (2 * ss * ss)) * exp(-(q - c) * (q - c) / (2 * sr * sr));
+                    num += wt * q;
+                    den += wt;
+                }
+            out[(size_t)i * w + j] = num / den;
+        }
+}
+
+/* Median (radius mr, skipped when 0) then bilateral (radius br, skipped
+ * when 0). */
+int orc_denoise(const double *img, int h, int w, int mr, int br, double ss, double sr, double *out)
+{
+    if (mr < 0 || mr > 4 || br < 0 || (br > 0 && !(ss > 0 && sr > 0))) return ORC_EINVAL;
+    const size_t n = (size_t)h * w;
+    double *tmp = (double *)malloc(sizeof(double) * n);
+    if (!tmp) return ORC_ENOMEM;
+    if (mr > 0) orc_median(img, h, w, mr, tmp);
+    else memcpy(tmp, img, sizeof(double) * n);
+    if (br > 0) orc_bilateral(tmp, h, w, br, ss, sr, out);
+    else memcpy(out, tmp, sizeof(double) * n);
+    free(tmp);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole path                                                                */
 /* ------------------------------------------------------------------------ */
 

@@ -119,6 +119,8 @@ struct Timing {
     std::vector<hipEvent_t> pool;
     double done_ms = 0, done_bytes = 0;
     int64_t done_n = 0, done_px = 0;
+    std::vector<double> rec_ms, rec_bytes;
+    std::vector<int64_t> rec_px;
 
     hipEvent_t get()
     {
@@ -932,6 +934,9 @@ roi_status roi_timing_read(double *total_ms, int64_t *launches, int64_t *pixels,
         g_timing.done_n += 1;
         g_timing.done_px += t.px;
         g_timing.done_bytes += t.bytes;
+        g_timing.rec_ms.push_back(ms);
+        g_timing.rec_px.push_back(t.px);
+        g_timing.rec_bytes.push_back(t.bytes);
         g_timing.pool.push_back(t.e0);
         g_timing.pool.push_back(t.e1);
     }
@@ -956,6 +961,22 @@ void roi_timing_reset(void)
     g_timing.done_bytes = 0;
     g_timing.done_n = 0;
     g_timing.done_px = 0;
+    g_timing.rec_ms.clear();
+    g_timing.rec_px.clear();
+    g_timing.rec_bytes.clear();
+}
+
+int32_t roi_timing_records(double *ms, int64_t *pixels, double *bytes, int32_t max)
+{
+    if (roi_timing_read(nullptr, nullptr, nullptr, nullptr) != ROI_OK) return -1;
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    const int32_t n = (int32_t)g_timing.rec_ms.size();
+    for (int32_t i = 0; i < n && i < max; ++i) {
+        if (ms) ms[i] = g_timing.rec_ms[i];
+        if (pixels) pixels[i] = g_timing.rec_px[i];
+        if (bytes) bytes[i] = g_timing.rec_bytes[i];
+    }
+    return n;
 }
 
 void roi_autotune(int32_t mode)

@@ -27,7 +27,7 @@ EXPORTED = [
     "roi_pyr_down", "roi_poly_expand", "roi_batched_workspace_size", "roi_mask_batched",
     "roi_stream_create", "roi_stream_push", "roi_stream_reset", "roi_stream_state_bytes",
     "roi_stream_destroy", "roi_stream_push_many", "roi_timing_enable", "roi_timing_read",
-    "roi_timing_reset", "roi_autotune", "roi_set_strip", "roi_tuned_strip", "roi_status_str",
+    "roi_timing_reset", "roi_timing_records", "roi_autotune", "roi_set_strip", "roi_tuned_strip", "roi_status_str",
     "roi_server_create", "roi_server_open_stream", "roi_server_close_stream", "roi_server_stream_bytes",
     "roi_server_submit", "roi_server_poll", "roi_server_drain", "roi_server_destroy",
 ]
@@ -113,6 +113,9 @@ def lib():
         L.roi_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                       ctypes.POINTER(ctypes.c_double)]
         L.roi_timing_read.restype = i32
+        L.roi_timing_records.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
+                                         ctypes.POINTER(ctypes.c_double), i32]
+        L.roi_timing_records.restype = i32
         L.roi_timing_reset.argtypes = []
         L.roi_timing_reset.restype = None
         L.roi_autotune.argtypes = [i32]
@@ -335,6 +338,16 @@ def timing_read():
     _check(lib().roi_timing_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(px), ctypes.byref(b)),
            "roi_timing_read")
     return ms.value, n.value, px.value, b.value
+
+
+def timing_records():
+    """[(kernel ms, output pixels, algorithmic bytes)] of every timed iteration launch."""
+    n = lib().roi_timing_records(None, None, None, 0)
+    if n < 0:
+        raise RoiError(ROI_EDEVICE, "roi_timing_records")
+    ms, px, b = (ctypes.c_double * n)(), (ctypes.c_int64 * n)(), (ctypes.c_double * n)()
+    lib().roi_timing_records(ms, px, b, n)
+    return list(zip(ms, px, b))
 
 
 def autotune(mode=1):

@@ -296,3 +296,47 @@ def test_dilate_single_pixel_gives_structuring_element():
         se = bf.structuring_element(r, shape).astype(np.uint8)
         np.testing.assert_array_equal(m[5 - r:6 + r, 5 - r:6 + r], se)
         assert m.sum() == se.sum()
+
+
+# --------------------------------------------------------------------------- denoising pre-stage
+
+@pytest.mark.parametrize("r", [1, 2])
+def test_median_matches_scipy(r):
+    from scipy import ndimage
+    img = np.random.default_rng(20).integers(0, 4096, (23, 31)).astype(np.float64)
+    np.testing.assert_array_equal(oracle.median(img, r), ndimage.median_filter(img, size=2 * r + 1, mode="nearest"))
+
+
+def test_bilateral_limits():
+    from scipy import ndimage
+    img = rnd((21, 26), 21, 50.0)
+    # huge range sigma: a normalised Gaussian blur
+    t = np.arange(-2, 3, dtype=np.float64)
+    k = np.exp(-t * t / (2 * 1.5 ** 2))
+    k /= k.sum()
+    blur = ndimage.correlate1d(ndimage.correlate1d(img, k, axis=0, mode="nearest"), k, axis=1, mode="nearest")
+    np.testing.assert_allclose(oracle.bilateral(img, 2, 1.5, 1e9), blur, atol=1e-9)
+    # tiny range sigma on distinct values: only the centre weighs
+    np.testing.assert_allclose(oracle.bilateral(img, 2, 1.5, 1e-6), img, atol=1e-12)
+    # constants stay constant
+    assert np.allclose(oracle.bilateral(np.full((9, 9), 7.5), 2, 1.5, 3.0), 7.5)
+
+
+def test_bilateral_matches_bruteforce():
+    img = rnd((13, 17), 22, 30.0)
+    ref = np.empty_like(img)
+    pad = np.pad(img, 2, mode="edge")
+    for i in range(13):
+        for j in range(17):
+            win = pad[i:i + 5, j:j + 5]
+            u, v = np.meshgrid(np.arange(-2, 3), np.arange(-2, 3), indexing="ij")
+            wt = np.exp(-(u * u + v * v) / (2 * 1.2 ** 2)) * np.exp(-(win - img[i, j]) ** 2 / (2 * 8.0 ** 2))
+            ref[i, j] = (wt * win).sum() / wt.sum()
+    np.testing.assert_allclose(oracle.bilateral(img, 2, 1.2, 8.0), ref, atol=1e-10)
+
+
+def test_denoise_composes_median_then_bilateral():
+    img = np.random.default_rng(23).integers(0, 255, (19, 22)).astype(np.float64)
+    np.testing.assert_array_equal(oracle.denoise(img, 1, 2, 1.5, 20.0),
+                                  oracle.bilateral(oracle.median(img, 1), 2, 1.5, 20.0))
+    np.testing.assert_array_equal(oracle.denoise(img, 0, 0), img)
