@@ -163,6 +163,8 @@ def main():
     }
 
     if not args.no_extras:
+        out["plain_denoise"] = bench_plain_variant(fl, frames, flows, masks, dev, args,
+                                                   fl.default_params(denoise=1, sigma_range=60.0), "denoise on")
         out["streaming"] = bench_streaming(fl, frames, p, dev, args)
         out["batched"] = bench_batched(fl, dev, args, fp16=False)
         out["batched_fp16"] = bench_batched(fl, dev, args, fp16=True)
@@ -174,6 +176,25 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(seq)
     print(json.dumps(out), flush=True)
+
+
+def bench_plain_variant(fl, frames, flows, masks, dev, args, p, name):
+    """The plain per-pair path with other parameters, over the same 63 pairs."""
+    import torch
+    npairs = len(frames) - 1
+    ws = fl.alloc_workspace(fl.workspace_size(H, W, fl.ROI_U16, p), dev)
+    for i in range(npairs):
+        fl.roi_mask(frames[i], frames[i + 1], p, flow=flows[i], mask=masks[i], ws=ws)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for i in range(npairs):
+            fl.roi_mask(frames[i], frames[i + 1], p, flow=flows[i], mask=masks[i], ws=ws)
+    torch.cuda.synchronize()
+    r = {"frames_per_s": round(npairs * reps / (time.perf_counter() - t0), 2), "params": name}
+    log("plain (%s): %.1f frames/s" % (name, r["frames_per_s"]))
+    return r
 
 
 def bench_streaming(fl, frames, p, dev, args):

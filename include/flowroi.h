@@ -81,10 +81,20 @@ typedef struct roi_params {
     int32_t dilate_radius; /* structuring-element radius, 0..32 */
     int32_t se_shape;      /* ROI_SE_SQUARE or ROI_SE_DISC */
     uint32_t flags;        /* ROI_USE_INITIAL_FLOW | ROI_FP16_STORAGE */
+    /* Denoising pre-stage (Method, Optical flow extraction: median then
+     * bilateral filtering; Table 1 "Denoise" on/off), applied to both
+     * frames before the pyramid. */
+    int32_t denoise;          /* 0 off, 1 on */
+    int32_t median_radius;    /* 0..2: (2r+1)^2 median, 0 skips it */
+    int32_t bilateral_radius; /* 0..3: (2r+1)^2 bilateral window, 0 skips it */
+    float sigma_space;        /* bilateral spatial sigma (pixels), > 0 */
+    float sigma_range;        /* bilateral range sigma (grey levels of the input), > 0 */
 } roi_params;
 
 /* Defaults: levels 3, winsize 15, iterations 3, poly_n 5, poly_sigma 1.1,
- * eps 1e-3, ABS threshold 1.0 px, square dilation of radius 2, no flags. */
+ * eps 1e-3, ABS threshold 1.0 px, square dilation of radius 2, no flags,
+ * denoising off (when on: 3x3 median, 5x5 bilateral, sigma_space 1.5,
+ * sigma_range 20). */
 void roi_default_params(roi_params *p);
 
 /* Host-only check of a request (no device work). ROI_OK, ROI_EINVAL for a
@@ -131,6 +141,13 @@ roi_status roi_pyr_down(const float *src, int32_t h, int32_t w, float *dst, void
  * stored values to FP16 precision). */
 roi_status roi_poly_expand(const void *img, int32_t h, int32_t w, int64_t pitch, roi_dtype dtype,
                            const roi_params *p, float *coef, void *stream);
+
+/* Denoising pre-stage of one frame: median of radius p->median_radius, then
+ * bilateral of radius p->bilateral_radius (sigma_space, sigma_range), both
+ * with replicated borders. out: device h*w floats (pitch w). Applies
+ * whatever p->denoise says (the stage runs regardless). */
+roi_status roi_denoise(const void *img, int32_t h, int32_t w, int64_t pitch, roi_dtype dtype, const roi_params *p,
+                       float *out, void *stream);
 
 /* ---- Batched: several pairs of uneven sizes in one captured launch ------ */
 

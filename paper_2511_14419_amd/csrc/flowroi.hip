@@ -60,6 +60,7 @@ struct Plan {
     size_t ts;        // storage bytes per expansion value
     size_t is;        // storage bytes per pyramid image value (FP64)
     Level lv[MAX_LEVELS];
+    size_t den[2];    // denoised level-0 frames (floats, pitch lv[0].pitch), when denoising
     size_t init_off;  // coarsest-level initial flow
     size_t m2_off;    // |d|^2 at full resolution, pitch lv[0].pitch
     size_t hist_off;  // radix-select histogram
@@ -96,6 +97,8 @@ Plan make_plan(int h, int w, const roi_params *p)
         v.fa = take(plane * sizeof(float2));
         v.fb = l > 0 ? take(plane * sizeof(float2)) : 0;
     }
+    for (int f = 0; f < 2; ++f)
+        pl.den[f] = p->denoise ? take((size_t)pl.lv[0].h * pl.lv[0].pitch * sizeof(float)) : 0;
     const Level &c = pl.lv[pl.L - 1];
     pl.init_off = take((size_t)c.h * c.pitch * sizeof(float2));
     pl.m2_off = take((size_t)pl.lv[0].h * pl.lv[0].pitch * sizeof(float));
@@ -231,26 +234,86 @@ void launch_poly_raw(roi_dtype dt, const PolyArgs &a, int frames, hipStream_t s)
     else launch_poly<float, TOut>(a, frames, s);
 }
 
+template <typename TIn, int MR>
+void launch_denoise_b(const DenoiseArgs &a, int br, int frames, hipStream_t s)
+{
+    dim3 g((a.w + DN_TW - 1) / DN_TW, (a.h + DN_TH - 1) / DN_TH, frames);
+    switch (br) {
+    case 0: hipLaunchKernelGGL((k_denoise<TIn, MR, 0>), g, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_denoise<TIn, MR, 1>), g, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_denoise<TIn, MR, 2>), g, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_denoise<TIn, MR, 3>), g, dim3(256), 0, s, a); break;
+    }
+}
+
+template <typename TIn>
+void launch_denoise_t(const DenoiseArgs &a, int mr, int br, int frames, hipStream_t s)
+{
+    if (mr == 0) launch_denoise_b<TIn, 0>(a, br, frames, s);
+    else if (mr == 1) launch_denoise_b<TIn, 1>(a, br, frames, s);
+    else launch_denoise_b<TIn, 2>(a, br, frames, s);
+}
+
+void fill_denoise(DenoiseArgs &a, const roi_params *p)
+{
+    const int br = p->bilateral_radius;
+    a.inv2sr2 = br > 0 ? (float)(1.0 / (2.0 * (double)p->sigma_range * (double)p->sigma_range)) : 0.f;
+    for (int u = -br; u <= br; ++u)
+        for (int v = -br; v <= br; ++v)
+            a.ws[(u + br) * (2 * DN_MAXB + 1) + (v + br)] =
+                (float)std::exp(-(double)(u * u + v * v) / (2.0 * (double)p->sigma_space * (double)p->sigma_space));
+}
+
+roi_status launch_denoise(roi_dtype dt, const DenoiseArgs &a, const roi_params *p, int frames, hipStream_t s)
+{
+    if (dt == ROI_U8) launch_denoise_t<uint8_t>(a, p->median_radius, p->bilateral_radius, frames, s);
+    else if (dt == ROI_U16) launch_denoise_t<uint16_t>(a, p->median_radius, p->bilateral_radius, frames, s);
+    else launch_denoise_t<float>(a, p->median_radius, p->bilateral_radius, frames, s);
+    LAUNCH_CHECK();
+    return ROI_OK;
+}
+
 // Pyramid and expansions of `nf` (1 or 2) frames into expansion sets `set[]`.
 roi_status enqueue_expand(const Plan &pl, uint8_t *base, int nf, const void *const *frames, int64_t pitch,
                           roi_dtype dt, const roi_params *p, const int *set, hipStream_t s)
 {
     const PolyConsts pc = poly_consts(p->poly_n, p->poly_sigma);
+    const void *lvl0[2] = {frames[0], nf > 1 ? frames[1] : nullptr};
+    roi_dtype dt0 = dt;
+    int64_t pitch0 = pitch;
+    if (p->denoise) {
+        DenoiseArgs da{};
+        fill_denoise(da, p);
+        for (int f = 0; f < nf; ++f) {
+            da.src[f] = frames[f];
+            da.dst[f] = (float *)(base + pl.den[set[f]]);
+            lvl0[f] = da.dst[f];
+        }
+        da.src_pitch = pitch;
+        da.dst_pitch = pl.lv[0].pitch;
+        da.h = pl.lv[0].h;
+        da.w = pl.lv[0].w;
+        roi_status st = launch_denoise(dt, da, p, nf, s);
+        if (st != ROI_OK) return st;
+        dt0 = ROI_F32; // denoised frames: floats in the input's grey levels
+        pitch0 = pl.lv[0].pitch;
+    }
+    const float dc0 = dc_of(dt); // the frame's DC constant, also for denoised frames
     for (int l = 1; l < pl.L; ++l) {
         const Level &src = pl.lv[l - 1], &dst = pl.lv[l];
         PyrArgs a{};
         for (int f = 0; f < nf; ++f) {
-            a.src[f] = l == 1 ? frames[f] : (const void *)(base + src.img[set[f]]);
+            a.src[f] = l == 1 ? lvl0[f] : (const void *)(base + src.img[set[f]]);
             a.dst[f] = base + dst.img[set[f]];
         }
-        a.src_pitch = l == 1 ? pitch : src.pitch;
-        a.dc = l == 1 ? dc_of(dt) : 0.0f;
+        a.src_pitch = l == 1 ? pitch0 : src.pitch;
+        a.dc = l == 1 ? dc0 : 0.0f;
         a.dst_pitch = dst.pitch;
         a.h = src.h;
         a.w = src.w;
         a.h2 = dst.h;
         a.w2 = dst.w;
-        if (l == 1) launch_pyr_raw<double>(dt, a, nf, s);
+        if (l == 1) launch_pyr_raw<double>(dt0, a, nf, s);
         else launch_pyr<double, double>(a, nf, s);
         LAUNCH_CHECK();
     }
@@ -259,22 +322,22 @@ roi_status enqueue_expand(const Plan &pl, uint8_t *base, int nf, const void *con
         PolyArgs a{};
         fill_poly(a, pc);
         for (int f = 0; f < nf; ++f) {
-            a.src[f] = l == 0 ? frames[f] : (const void *)(base + v.img[set[f]]);
+            a.src[f] = l == 0 ? lvl0[f] : (const void *)(base + v.img[set[f]]);
             a.dst[f] = base + v.r4[set[f]];
             a.dst1[f] = base + v.r1[set[f]];
         }
         a.packed = 1;
-        a.src_pitch = l == 0 ? pitch : v.pitch;
-        a.dc = l == 0 ? dc_of(dt) : 0.0f;
+        a.src_pitch = l == 0 ? pitch0 : v.pitch;
+        a.dc = l == 0 ? dc0 : 0.0f;
         a.dplane = (int64_t)v.h * v.pitch;
         a.dpitch = v.pitch;
         a.h = v.h;
         a.w = v.w;
         if (pl.fp16) {
-            if (l == 0) launch_poly_raw<__half>(dt, a, nf, s);
+            if (l == 0) launch_poly_raw<__half>(dt0, a, nf, s);
             else launch_poly<double, __half>(a, nf, s);
         } else {
-            if (l == 0) launch_poly_raw<float>(dt, a, nf, s);
+            if (l == 0) launch_poly_raw<float>(dt0, a, nf, s);
             else launch_poly<double, float>(a, nf, s);
         }
         LAUNCH_CHECK();
@@ -599,6 +662,11 @@ void roi_default_params(roi_params *p)
     p->dilate_radius = 2;
     p->se_shape = ROI_SE_SQUARE;
     p->flags = 0;
+    p->denoise = 0;
+    p->median_radius = 1;
+    p->bilateral_radius = 2;
+    p->sigma_space = 1.5f;
+    p->sigma_range = 20.0f;
 }
 
 roi_status roi_validate(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p)
@@ -620,6 +688,12 @@ roi_status roi_validate(int32_t h, int32_t w, roi_dtype dtype, const roi_params 
     if (p->dilate_radius < 0) return ROI_EINVAL;
     if (p->se_shape != ROI_SE_SQUARE && p->se_shape != ROI_SE_DISC) return ROI_EINVAL;
     if (p->flags & ~(uint32_t)(ROI_USE_INITIAL_FLOW | ROI_FP16_STORAGE)) return ROI_EINVAL;
+    if (p->denoise != 0 && p->denoise != 1) return ROI_EINVAL;
+    if (p->denoise) {
+        if (p->median_radius < 0 || p->bilateral_radius < 0) return ROI_EINVAL;
+        if (p->bilateral_radius > 0 && !(finite_pos(p->sigma_space) && finite_pos(p->sigma_range))) return ROI_EINVAL;
+        if (p->median_radius > DN_MAXM || p->bilateral_radius > DN_MAXB) return ROI_EUNSUPPORTED;
+    }
     if (p->winsize > 2 * IT_MAXR + 1) return ROI_EUNSUPPORTED;
     if (p->dilate_radius > DIL_MAXR) return ROI_EUNSUPPORTED;
     if (h > 32768 || w > 32768) return ROI_EUNSUPPORTED;
@@ -705,6 +779,27 @@ roi_status roi_poly_expand(const void *img, int32_t h, int32_t w, int64_t pitch,
     launch_poly_raw<float>(dtype, a, 1, (hipStream_t)stream);
     LAUNCH_CHECK();
     return ROI_OK;
+}
+
+roi_status roi_denoise(const void *img, int32_t h, int32_t w, int64_t pitch, roi_dtype dtype, const roi_params *p,
+                       float *out, void *stream)
+{
+    if (!p) return ROI_EINVAL;
+    roi_params q = *p;
+    q.denoise = 1;
+    roi_status st = roi_validate(h, w, dtype, &q);
+    if (st != ROI_OK) return st;
+    if (h == 0 || w == 0) return ROI_OK;
+    if (!img || !out || pitch < w) return ROI_EINVAL;
+    DenoiseArgs da{};
+    fill_denoise(da, &q);
+    da.src[0] = img;
+    da.dst[0] = out;
+    da.src_pitch = pitch;
+    da.dst_pitch = w;
+    da.h = h;
+    da.w = w;
+    return launch_denoise(dtype, da, &q, 1, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------- batched

@@ -161,6 +161,120 @@ __global__ __launch_bounds__(256) void k_pyr_down(PyrArgs a)
     }
 }
 
+// ---------------------------------------------------------------- denoising pre-stage
+
+constexpr int DN_TW = 64, DN_TH = 16, DN_MAXM = 2, DN_MAXB = 3;
+
+struct DenoiseArgs {
+    const void *src[2];
+    int64_t src_pitch;
+    float *dst[2];
+    int32_t dst_pitch;
+    int32_t h, w;
+    float inv2sr2;                                       // 1 / (2 sigma_range^2)
+    float ws[(2 * DN_MAXB + 1) * (2 * DN_MAXB + 1)];     // spatial weights exp(-|t|^2 / (2 sigma_space^2))
+};
+
+__device__ __forceinline__ void cswap(float &a, float &b)
+{
+    const float lo = fminf(a, b), hi = fmaxf(a, b);
+    a = lo;
+    b = hi;
+}
+
+// exact median of 9 (compare-exchange network, Devillard's median search)
+__device__ __forceinline__ float median9(float p[9])
+{
+    cswap(p[1], p[2]); cswap(p[4], p[5]); cswap(p[7], p[8]);
+    cswap(p[0], p[1]); cswap(p[3], p[4]); cswap(p[6], p[7]);
+    cswap(p[1], p[2]); cswap(p[4], p[5]); cswap(p[7], p[8]);
+    cswap(p[0], p[3]); cswap(p[5], p[8]); cswap(p[4], p[7]);
+    cswap(p[3], p[6]); cswap(p[1], p[4]); cswap(p[2], p[5]);
+    cswap(p[4], p[7]); cswap(p[4], p[2]); cswap(p[6], p[4]);
+    cswap(p[4], p[2]);
+    return p[4];
+}
+
+// Median of radius MR then bilateral of radius BR, replicate borders at both
+// stages (the bilateral sees the median image extended by its edge pixels,
+// exactly as filtering the whole median image would). Values stay in the
+// input's grey levels.
+// grid: (ceil(w/64), ceil(h/16), frames)
+template <typename TIn, int MR, int BR>
+__global__ __launch_bounds__(256) void k_denoise(DenoiseArgs a)
+{
+    constexpr int HALO = MR + BR;
+    constexpr int RW = DN_TW + 2 * HALO, RH = DN_TH + 2 * HALO; // raw region
+    constexpr int MW = DN_TW + 2 * BR, MH = DN_TH + 2 * BR;     // median region
+    __shared__ float raw[RH][RW + 1];
+    __shared__ float med[MH][MW + 1];
+    const TIn *src = (const TIn *)a.src[blockIdx.z];
+    const int x0 = blockIdx.x * DN_TW, y0 = blockIdx.y * DN_TH;
+    const int xb = x0 - HALO, yb = y0 - HALO; // image position of raw[0][0]
+    for (int i = threadIdx.x; i < RH * RW; i += 256) {
+        const int r = i / RW, c = i - r * RW;
+        raw[r][c] = ld(src, (size_t)clampi(yb + r, 0, a.h - 1) * a.src_pitch + clampi(xb + c, 0, a.w - 1));
+    }
+    __syncthreads();
+    // median image at the clamped positions the bilateral window reaches;
+    // an in-frame row r sits at raw row r - yb
+    for (int i = threadIdx.x; i < MH * MW; i += 256) {
+        const int r = i / MW, c = i - r * MW;
+        const int cy = clampi(y0 - BR + r, 0, a.h - 1), cx = clampi(x0 - BR + c, 0, a.w - 1);
+        float m;
+        if (MR == 0) {
+            m = raw[cy - yb][cx - xb];
+        } else if (MR == 1) {
+            float p[9];
+#pragma unroll
+            for (int u = -1; u <= 1; ++u)
+#pragma unroll
+                for (int v = -1; v <= 1; ++v)
+                    p[(u + 1) * 3 + v + 1] = raw[clampi(cy + u, 0, a.h - 1) - yb][clampi(cx + v, 0, a.w - 1) - xb];
+            m = median9(p);
+        } else {
+            constexpr int N = (2 * MR + 1) * (2 * MR + 1);
+            float p[N];
+            int k = 0;
+#pragma unroll
+            for (int u = -MR; u <= MR; ++u)
+#pragma unroll
+                for (int v = -MR; v <= MR; ++v) p[k++] = raw[clampi(cy + u, 0, a.h - 1) - yb][clampi(cx + v, 0, a.w - 1) - xb];
+            // odd-even transposition sort (exact)
+#pragma unroll
+            for (int pass = 0; pass < N; ++pass)
+#pragma unroll
+                for (int q = pass & 1; q + 1 < N; q += 2) cswap(p[q], p[q + 1]);
+            m = p[N / 2];
+        }
+        med[r][c] = m;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < DN_TH * DN_TW; i += 256) {
+        const int r = i / DN_TW, c = i - r * DN_TW;
+        const int y = y0 + r, x = x0 + c;
+        if (y >= a.h || x >= a.w) continue;
+        float o;
+        if (BR == 0) {
+            o = med[r][c];
+        } else {
+            const float ctr = med[r + BR][c + BR];
+            float num = 0.f, den = 0.f;
+#pragma unroll
+            for (int u = 0; u <= 2 * BR; ++u)
+#pragma unroll
+                for (int v = 0; v <= 2 * BR; ++v) {
+                    const float q = med[r + u][c + v], e = q - ctr;
+                    const float wt = a.ws[u * (2 * DN_MAXB + 1) + v] * expf(-e * e * a.inv2sr2);
+                    num += wt * q;
+                    den += wt;
+                }
+            o = num / den;
+        }
+        a.dst[blockIdx.z][(size_t)y * a.dst_pitch + x] = o;
+    }
+}
+
 // ---------------------------------------------------------------- polynomial expansion
 
 constexpr int PE_TW = 64, PE_TH = 16, PE_MAXN = 3;

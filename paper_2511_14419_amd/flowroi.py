@@ -24,7 +24,7 @@ ROI_USE_INITIAL_FLOW, ROI_FP16_STORAGE = 1, 2
 
 EXPORTED = [
     "roi_default_params", "roi_validate", "roi_workspace_size", "roi_mask", "roi_read_tau2",
-    "roi_pyr_down", "roi_poly_expand", "roi_batched_workspace_size", "roi_mask_batched",
+    "roi_pyr_down", "roi_poly_expand", "roi_denoise", "roi_batched_workspace_size", "roi_mask_batched",
     "roi_stream_create", "roi_stream_push", "roi_stream_reset", "roi_stream_state_bytes",
     "roi_stream_destroy", "roi_stream_push_many", "roi_timing_enable", "roi_timing_read",
     "roi_timing_reset", "roi_timing_records", "roi_autotune", "roi_set_strip", "roi_tuned_strip", "roi_status_str",
@@ -43,7 +43,9 @@ class RoiParams(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("winsize", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("poly_n", ctypes.c_int32), ("poly_sigma", ctypes.c_float), ("eps", ctypes.c_float),
                 ("thresh_mode", ctypes.c_int32), ("thresh", ctypes.c_float),
-                ("dilate_radius", ctypes.c_int32), ("se_shape", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("dilate_radius", ctypes.c_int32), ("se_shape", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("denoise", ctypes.c_int32), ("median_radius", ctypes.c_int32), ("bilateral_radius", ctypes.c_int32),
+                ("sigma_space", ctypes.c_float), ("sigma_range", ctypes.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +93,8 @@ def lib():
         L.roi_pyr_down.restype = i32
         L.roi_poly_expand.argtypes = [vp, i32, i32, i64, i32, pp, vp, vp]
         L.roi_poly_expand.restype = i32
+        L.roi_denoise.argtypes = [vp, i32, i32, i64, i32, pp, vp, vp]
+        L.roi_denoise.restype = i32
         L.roi_batched_workspace_size.argtypes = [i32, ctypes.POINTER(RoiPair), i32, pp]
         L.roi_batched_workspace_size.restype = sz
         L.roi_mask_batched.argtypes = [i32, ctypes.POINTER(RoiPair), i32, pp, vp, sz, vp]
@@ -254,6 +258,16 @@ def poly_expand(img, params=None, stream=None):
                                  dtype_code(img.dtype), ctypes.byref(params), ctypes.c_void_p(coef.data_ptr()),
                                  _stream(stream)), "roi_poly_expand")
     return coef
+
+
+def denoise(img, params=None, stream=None):
+    """Median then bilateral filter of one device frame -> (h, w) float32."""
+    params = params or default_params()
+    h, w = img.shape
+    out = torch.empty((h, w), dtype=torch.float32, device=img.device)
+    _check(lib().roi_denoise(ctypes.c_void_p(img.data_ptr()), h, w, _frame_pitch(img), dtype_code(img.dtype),
+                             ctypes.byref(params), ctypes.c_void_p(out.data_ptr()), _stream(stream)), "roi_denoise")
+    return out
 
 
 def make_pairs(prevs, nexts, flows, masks):

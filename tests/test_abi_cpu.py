@@ -39,6 +39,8 @@ def test_defaults(F):
     assert (p.levels, p.winsize, p.iterations, p.poly_n) == (3, 15, 3, 5)
     assert abs(p.poly_sigma - 1.1) < 1e-6 and abs(p.eps - 1e-3) < 1e-9
     assert (p.thresh_mode, p.thresh, p.dilate_radius, p.se_shape, p.flags) == (0, 1.0, 2, 0, 0)
+    assert (p.denoise, p.median_radius, p.bilateral_radius) == (0, 1, 2)
+    assert abs(p.sigma_space - 1.5) < 1e-6 and abs(p.sigma_range - 20.0) < 1e-6
 
 
 @pytest.mark.parametrize("kw,h,w,dtype,expect", [
@@ -66,6 +68,13 @@ def test_defaults(F):
     ({"flags": 8}, 64, 64, 0, -1),
     ({"flags": 3}, 64, 64, 2, 0),
     ({}, 40000, 64, 0, -4),
+    ({"denoise": 1}, 64, 64, 0, 0),
+    ({"denoise": 2}, 64, 64, 0, -1),
+    ({"denoise": 1, "median_radius": 3}, 64, 64, 0, -4),
+    ({"denoise": 1, "bilateral_radius": 4}, 64, 64, 0, -4),
+    ({"denoise": 1, "sigma_range": 0.0}, 64, 64, 0, -1),
+    ({"denoise": 1, "bilateral_radius": 0, "sigma_range": 0.0}, 64, 64, 0, 0),
+    ({"denoise": 0, "median_radius": 9}, 64, 64, 0, 0),
 ])
 def test_validate(F, kw, h, w, dtype, expect):
     assert F.validate(h, w, dtype, F.default_params(**kw)) == expect
