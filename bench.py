@@ -166,6 +166,7 @@ def main():
         out["plain_denoise"] = bench_plain_variant(fl, frames, flows, masks, dev, args,
                                                    fl.default_params(denoise=1, sigma_range=60.0), "denoise on")
         out["streaming"] = bench_streaming(fl, frames, p, dev, args)
+        out["streaming_adjacent2"] = bench_streaming(fl, frames, fl.default_params(adjacent=2), dev, args)
         out["batched"] = bench_batched(fl, dev, args, fp16=False)
         out["batched_fp16"] = bench_batched(fl, dev, args, fp16=True)
         if not args.no_serving:

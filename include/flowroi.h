@@ -89,6 +89,11 @@ typedef struct roi_params {
     int32_t bilateral_radius; /* 0..3: (2r+1)^2 bilateral window, 0 skips it */
     float sigma_space;        /* bilateral spatial sigma (pixels), > 0 */
     float sigma_range;        /* bilateral range sigma (grey levels of the input), > 0 */
+    /* Adjacent factor (Table 1; Region of Interest extraction: masks of
+     * neighbouring frames join the current one when motion is weak). Stream
+     * contexts only: the mask of frame t becomes the union of its own mask
+     * and those of the previous `adjacent` frames of the stream. 0..8. */
+    int32_t adjacent;
 } roi_params;
 
 /* Defaults: levels 3, winsize 15, iterations 3, poly_n 5, poly_sigma 1.1,

@@ -241,3 +241,16 @@ def roi_mask(prev, next, levels=3, winsize=15, iterations=3, poly_n=5, poly_sigm
                                 int(dilate_radius), int(se_shape), _ptr(fl), _ptr(mask, _u8p),
                                 ctypes.byref(t2)))
     return fl, mask, t2.value
+
+
+def ensemble(masks, adjacent):
+    """Adjacent-frame ensemble (FlowRoI, Region of Interest extraction; the
+    adjacent factor of Table 1): the output for frame t is the union of the
+    frame's own mask and those of the previous `adjacent` frames."""
+    out = []
+    for t in range(len(masks)):
+        m = np.zeros_like(masks[t], dtype=np.uint8)
+        for k in range(max(0, t - adjacent), t + 1):
+            m |= masks[k].astype(np.uint8)
+        out.append(m)
+    return out

@@ -667,6 +667,7 @@ void roi_default_params(roi_params *p)
     p->bilateral_radius = 2;
     p->sigma_space = 1.5f;
     p->sigma_range = 20.0f;
+    p->adjacent = 0;
 }
 
 roi_status roi_validate(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p)
@@ -689,6 +690,8 @@ roi_status roi_validate(int32_t h, int32_t w, roi_dtype dtype, const roi_params 
     if (p->se_shape != ROI_SE_SQUARE && p->se_shape != ROI_SE_DISC) return ROI_EINVAL;
     if (p->flags & ~(uint32_t)(ROI_USE_INITIAL_FLOW | ROI_FP16_STORAGE)) return ROI_EINVAL;
     if (p->denoise != 0 && p->denoise != 1) return ROI_EINVAL;
+    if (p->adjacent < 0) return ROI_EINVAL;
+    if (p->adjacent > ENS_MAX) return ROI_EUNSUPPORTED;
     if (p->denoise) {
         if (p->median_radius < 0 || p->bilateral_radius < 0) return ROI_EINVAL;
         if (p->bilateral_radius > 0 && !(finite_pos(p->sigma_space) && finite_pos(p->sigma_range))) return ROI_EINVAL;
@@ -911,12 +914,15 @@ struct roi_stream_ctx {
     int primed;     // a previous frame's expansion is resident
     int cur;        // expansion set holding the previous frame
     int device;
+    uint8_t *hist;  // adjacent > 0: ring of the last `adjacent` own masks (h*w bytes each)
+    int hist_count; // masks stored since the last reset (capped at adjacent)
+    int hist_pos;   // ring slot the next mask goes to
 };
 
 size_t roi_stream_state_bytes(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p)
 {
     if (roi_validate(h, w, dtype, p) != ROI_OK || h == 0 || w == 0) return 0;
-    return HDR_BYTES + make_plan(h, w, p).bytes;
+    return HDR_BYTES + make_plan(h, w, p).bytes + (size_t)p->adjacent * align_up((size_t)h * w, ALIGN);
 }
 
 roi_status roi_stream_create(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p, void **out_ctx)
@@ -938,6 +944,15 @@ roi_status roi_stream_create(int32_t h, int32_t w, roi_dtype dtype, const roi_pa
         delete c;
         return ROI_ENOMEM;
     }
+    c->hist = nullptr;
+    c->hist_count = 0;
+    c->hist_pos = 0;
+    // history slots on 256-byte boundaries (the union kernel moves 16 bytes at a time)
+    if (p->adjacent > 0 && hipMalloc((void **)&c->hist, (size_t)p->adjacent * align_up((size_t)h * w, ALIGN)) != hipSuccess) {
+        hipFree(c->buf);
+        delete c;
+        return ROI_ENOMEM;
+    }
     c->primed = 0;
     c->cur = 0;
     *out_ctx = c;
@@ -948,6 +963,7 @@ roi_status roi_stream_reset(void *ctx)
 {
     if (!ctx) return ROI_EINVAL;
     ((roi_stream_ctx *)ctx)->primed = 0;
+    ((roi_stream_ctx *)ctx)->hist_count = 0;
     return ROI_OK;
 }
 
@@ -956,6 +972,7 @@ void roi_stream_destroy(void *ctx)
     if (!ctx) return;
     roi_stream_ctx *c = (roi_stream_ctx *)ctx;
     hipFree(c->buf);
+    if (c->hist) hipFree(c->hist);
     delete c;
 }
 
@@ -978,6 +995,21 @@ static roi_status stream_push_one(roi_stream_ctx *c, const void *frame, int64_t 
     st = enqueue_flow(c->plan, base, (SelState *)c->buf, c->cur, nxt, c->h, c->w, &c->p, flow, mask, s);
     if (st != ROI_OK) return st;
     c->cur = nxt;
+    if (c->p.adjacent > 0 && mask) {
+        // union with the stream's previous masks, then remember this one
+        const size_t n = (size_t)c->h * c->w, slot = align_up(n, ALIGN);
+        const int K = c->p.adjacent;
+        EnsembleArgs ea{};
+        ea.mask = mask;
+        ea.store = c->hist + (size_t)c->hist_pos * slot;
+        ea.n = c->hist_count;
+        for (int k = 0; k < ea.n; ++k) ea.prev[k] = c->hist + (size_t)((c->hist_pos - 1 - k + K) % K) * slot;
+        ea.count = (int64_t)n;
+        hipLaunchKernelGGL(k_ensemble, dim3((unsigned)((n + 4095) / 4096)), dim3(256), 0, s, ea);
+        LAUNCH_CHECK();
+        c->hist_pos = (c->hist_pos + 1) % K;
+        if (c->hist_count < K) c->hist_count += 1;
+    }
     return ROI_OK;
 }
 

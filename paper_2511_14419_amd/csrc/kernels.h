@@ -854,4 +854,48 @@ __global__ __launch_bounds__(256) void k_dilate(DilArgs a)
     }
 }
 
+// ---------------------------------------------------------------- adjacent-frame ensemble
+
+constexpr int ENS_MAX = 8;
+
+struct EnsembleArgs {
+    uint8_t *mask;               // current mask in, union out (pitch w)
+    uint8_t *store;              // history slot that receives the current mask
+    const uint8_t *prev[ENS_MAX]; // previous masks to join (n of them)
+    int32_t n;
+    int64_t count;               // h * w
+};
+
+// history slot <- mask; mask <- mask | prev[0] | ... | prev[n-1]
+// (history slots start on 256-byte boundaries, so they share the mask's
+// 16-byte alignment test)
+// grid: ceil(count / 4096) blocks of 256 threads, 16 bytes per thread
+__global__ __launch_bounds__(256) void k_ensemble(EnsembleArgs a)
+{
+    const int64_t base = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+    // every previous mask is read before the slot is written: once the ring
+    // is full the slot receiving this mask holds the oldest one still joined
+    if (base + 16 <= a.count && ((uintptr_t)(a.mask + base) & 15) == 0) {
+        const uint4 own = *(const uint4 *)(a.mask + base);
+        uint4 m = own;
+        for (int k = 0; k < a.n; ++k) {
+            const uint4 q = *(const uint4 *)(a.prev[k] + base);
+            m.x |= q.x;
+            m.y |= q.y;
+            m.z |= q.z;
+            m.w |= q.w;
+        }
+        *(uint4 *)(a.store + base) = own;
+        *(uint4 *)(a.mask + base) = m;
+    } else {
+        for (int64_t i = base; i < base + 16 && i < a.count; ++i) {
+            const uint8_t own = a.mask[i];
+            uint8_t m = own;
+            for (int k = 0; k < a.n; ++k) m |= a.prev[k][i];
+            a.store[i] = own;
+            a.mask[i] = m;
+        }
+    }
+}
+
 } // namespace flowroi

@@ -45,7 +45,7 @@ class RoiParams(ctypes.Structure):
                 ("thresh_mode", ctypes.c_int32), ("thresh", ctypes.c_float),
                 ("dilate_radius", ctypes.c_int32), ("se_shape", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("denoise", ctypes.c_int32), ("median_radius", ctypes.c_int32), ("bilateral_radius", ctypes.c_int32),
-                ("sigma_space", ctypes.c_float), ("sigma_range", ctypes.c_float)]
+                ("sigma_space", ctypes.c_float), ("sigma_range", ctypes.c_float), ("adjacent", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

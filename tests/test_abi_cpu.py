@@ -75,6 +75,9 @@ def test_defaults(F):
     ({"denoise": 1, "sigma_range": 0.0}, 64, 64, 0, -1),
     ({"denoise": 1, "bilateral_radius": 0, "sigma_range": 0.0}, 64, 64, 0, 0),
     ({"denoise": 0, "median_radius": 9}, 64, 64, 0, 0),
+    ({"adjacent": 2}, 64, 64, 0, 0),
+    ({"adjacent": -1}, 64, 64, 0, -1),
+    ({"adjacent": 9}, 64, 64, 0, -4),
 ])
 def test_validate(F, kw, h, w, dtype, expect):
     assert F.validate(h, w, dtype, F.default_params(**kw)) == expect

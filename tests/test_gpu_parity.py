@@ -397,3 +397,33 @@ def test_fp16_storage_error_reported():
         % (err.max(), err.mean(), 100 * flips.mean()))
     assert np.isfinite(flow).all()
     assert err.mean() < 2e-3 and err.max() < 0.1
+
+
+def test_stream_adjacent_ensemble():
+    """Adjacent factor k: the stream's mask of frame t is the union of the own
+    masks of frames t-k..t (each own mask is roi_mask of its pair)."""
+    dev = device()
+    fl = F()
+    seq = synth.sequence_u16(150, 170, 7, 10, 33)
+    frames = [to_dev(f, dev) for f in seq]
+    own = [None]
+    p0 = fl.default_params(thresh=0.5)
+    for t in range(1, 7):
+        _, m, _ = fl.roi_mask(frames[t - 1], frames[t], p0)
+        own.append(m.cpu().numpy())
+    for k in (1, 3):
+        st = fl.Stream(150, 170, fl.ROI_U16, fl.default_params(thresh=0.5, adjacent=k))
+        flow = torch.empty((150, 170, 2), device=dev)
+        mask = torch.empty((150, 170), dtype=torch.uint8, device=dev)
+        assert st.push(frames[0], flow, mask) == fl.ROI_PRIMED
+        ref = oracle.ensemble(own[1:], k)
+        for t in range(1, 7):
+            st.push(frames[t], flow, mask)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(mask.cpu().numpy(), ref[t - 1])
+        st.reset()  # history forgotten: the next mask is the pair's own
+        st.push(frames[2], flow, mask)
+        st.push(frames[3], flow, mask)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(mask.cpu().numpy(), own[3])
+        st.close()

@@ -340,3 +340,14 @@ def test_denoise_composes_median_then_bilateral():
     np.testing.assert_array_equal(oracle.denoise(img, 1, 2, 1.5, 20.0),
                                   oracle.bilateral(oracle.median(img, 1), 2, 1.5, 20.0))
     np.testing.assert_array_equal(oracle.denoise(img, 0, 0), img)
+
+
+def test_ensemble_is_union_of_recent_masks():
+    rng = np.random.default_rng(30)
+    masks = [(rng.uniform(size=(7, 9)) > 0.8).astype(np.uint8) for _ in range(6)]
+    for k in (0, 1, 2, 5):
+        out = oracle.ensemble(masks, k)
+        for t in range(6):
+            ref = np.logical_or.reduce(masks[max(0, t - k):t + 1]).astype(np.uint8)
+            np.testing.assert_array_equal(out[t], ref)
+    assert all(np.array_equal(a, b) for a, b in zip(oracle.ensemble(masks, 0), masks))
