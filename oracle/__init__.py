@@ -77,6 +77,9 @@ def _load():
             lib.orc_bilateral.argtypes = [_dp, i, i, i, d, d, _dp]
             lib.orc_denoise.argtypes = [_dp, i, i, i, i, d, d, _dp]
             lib.orc_denoise.restype = i
+            lib.orc_saliency.argtypes = [_dp, i, i, d, _dp]
+            lib.orc_open_close.argtypes = [_u8p, i, i, i, _u8p]
+            lib.orc_cc_filter.argtypes = [_u8p, i, i, i, _u8p]
             _lib = lib
     return _lib
 
@@ -218,6 +221,47 @@ def denoise(img, median_radius=1, bilateral_radius=2, sigma_space=1.5, sigma_ran
     _check(_load().orc_denoise(_ptr(img), h, w, int(median_radius), int(bilateral_radius), float(sigma_space),
                                float(sigma_range), _ptr(out)))
     return out
+
+
+def saliency(flow, weight=0.7):
+    """Normalised motion saliency of a flow field (h, w, 2) -> (h, w)."""
+    flow = _f64(flow)
+    h, w = flow.shape[:2]
+    out = np.empty((h, w))
+    _load().orc_saliency(_ptr(flow), h, w, float(weight), _ptr(out))
+    return out
+
+
+def open_close(pre, radius=1):
+    pre = np.ascontiguousarray(pre, dtype=np.uint8)
+    h, w = pre.shape
+    out = np.empty_like(pre)
+    _load().orc_open_close(_ptr(pre, _u8p), h, w, int(radius), _ptr(out, _u8p))
+    return out
+
+
+def cc_filter(mask, min_area):
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    h, w = mask.shape
+    out = np.empty_like(mask)
+    _load().orc_cc_filter(_ptr(mask, _u8p), h, w, int(min_area), _ptr(out, _u8p))
+    return out
+
+
+def saliency_mask(flow, thresh_mode=1, thresh=0.2, weight=0.7, morph_radius=1, min_area=32, dilate_radius=2,
+                  se_shape=0):
+    """The paper's RoI rule on a flow field: saliency -> threshold (top
+    fraction or absolute on the normalised saliency) -> opening + closing ->
+    small-component removal -> dilation. Returns (mask, saliency, tau)."""
+    s = saliency(flow, weight)
+    if thresh_mode == 1:
+        k = int(np.floor(float(thresh) * s.size))
+        tau = np.sort(s.ravel())[::-1][k]
+    else:
+        tau = float(thresh)
+    pre = (s > tau).astype(np.uint8)
+    m = cc_filter(open_close(pre, morph_radius), min_area)
+    return dilate(m, dilate_radius, se_shape), s, tau
 
 
 def roi_mask(prev, next, levels=3, winsize=15, iterations=3, poly_n=5, poly_sigma=1.1, eps=1e-3,

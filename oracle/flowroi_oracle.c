@@ -549,6 +549,110 @@ int orc_denoise(const double *img, int h, int w, int mr, int br, double ss, doub
 }
 
 /* ------------------------------------------------------------------------ */
+/* The paper's RoI rule (Region of Interest extraction): motion saliency from */
+/* flow magnitude and its spatial gradient, normalisation, quantile          */
+/* threshold, opening and closing, removal of small connected components.    */
+/* ------------------------------------------------------------------------ */
+
+/* Saliency: M = |d|; G = |grad M| by central differences with replicated
+ * edges; S = wt M / max M + (1 - wt) G / max G (a term whose maximum is 0
+ * contributes 0); output S / max S (0 where max S = 0). */
+void orc_saliency(const double *flow, int h, int w, double wt, double *sal)
+{
+    const size_t n = (size_t)h * w;
+    double *M = (double *)malloc(sizeof(double) * n), *G = (double *)malloc(sizeof(double) * n);
+    double mM = 0.0, mG = 0.0, mS = 0.0;
+    for (size_t p = 0; p < n; ++p) {
+        M[p] = sqrt(flow[2 * p] * flow[2 * p] + flow[2 * p + 1] * flow[2 * p + 1]);
+        if (M[p] > mM) mM = M[p];
+    }
+    for (int i = 0; i < h; ++i)
+        for (int j = 0; j < w; ++j) {
+            const double gx = 0.5 * (M[(size_t)i * w + clampi(j + 1, 0, w - 1)] - M[(size_t)i * w + clampi(j - 1, 0, w - 1)]);
+            const double gy = 0.5 * (M[(size_t)clampi(i + 1, 0, h - 1) * w + j] - M[(size_t)clampi(i - 1, 0, h - 1) * w + j]);
+            G[(size_t)i * w + j] = sqrt(gx * gx + gy * gy);
+            if (G[(size_t)i * w + j] > mG) mG = G[(size_t)i * w + j];
+        }
+    for (size_t p = 0; p < n; ++p) {
+        const double a = mM > 0 ? M[p] / mM : 0.0, b = mG > 0 ? G[p] / mG : 0.0;
+        sal[p] = wt * a + (1.0 - wt) * b;
+        if (sal[p] > mS) mS = sal[p];
+    }
+    for (size_t p = 0; p < n; ++p) sal[p] = mS > 0 ? sal[p] / mS : 0.0;
+    free(M);
+    free(G);
+}
+
+/* Binary erosion (erode = 1) or dilation (erode = 0) by the (2r+1)^2 square,
+ * over the part of the square inside the frame. */
+static void morph_square(const uint8_t *in, int h, int w, int r, int erode, uint8_t *out)
+{
+    for (int i = 0; i < h; ++i)
+        for (int j = 0; j < w; ++j) {
+            uint8_t v = erode ? 1 : 0;
+            for (int u = -r; u <= r; ++u)
+                for (int q = -r; q <= r; ++q) {
+                    const int y = i + u, x = j + q;
+                    if (y < 0 || y >= h || x < 0 || x >= w) continue;
+                    if (erode && !in[(size_t)y * w + x]) v = 0;
+                    if (!erode && in[(size_t)y * w + x]) v = 1;
+                }
+            out[(size_t)i * w + j] = v;
+        }
+}
+
+/* Opening (erode, dilate) then closing (dilate, erode), square of radius r. */
+void orc_open_close(const uint8_t *pre, int h, int w, int r, uint8_t *out)
+{
+    const size_t n = (size_t)h * w;
+    uint8_t *a = (uint8_t *)malloc(n), *b = (uint8_t *)malloc(n);
+    morph_square(pre, h, w, r, 1, a);
+    morph_square(a, h, w, r, 0, b);
+    morph_square(b, h, w, r, 0, a);
+    morph_square(a, h, w, r, 1, out);
+    free(a);
+    free(b);
+}
+
+/* Keep the 8-connected components of `mask` whose area is >= min_area.
+ * Labels by depth-first flood fill. */
+void orc_cc_filter(const uint8_t *mask, int h, int w, int min_area, uint8_t *out)
+{
+    const size_t n = (size_t)h * w;
+    int *lab = (int *)malloc(sizeof(int) * n);
+    size_t *stack = (size_t *)malloc(sizeof(size_t) * n);
+    size_t *members = (size_t *)malloc(sizeof(size_t) * n);
+    for (size_t p = 0; p < n; ++p) lab[p] = -1;
+    memset(out, 0, n);
+    for (size_t s0 = 0; s0 < n; ++s0) {
+        if (!mask[s0] || lab[s0] >= 0) continue;
+        size_t top = 0, cnt = 0;
+        stack[top++] = s0;
+        lab[s0] = 1;
+        while (top) {
+            const size_t p = stack[--top];
+            members[cnt++] = p;
+            const int i = (int)(p / w), j = (int)(p % w);
+            for (int u = -1; u <= 1; ++u)
+                for (int v = -1; v <= 1; ++v) {
+                    const int y = i + u, x = j + v;
+                    if (y < 0 || y >= h || x < 0 || x >= w) continue;
+                    const size_t q = (size_t)y * w + x;
+                    if (mask[q] && lab[q] < 0) {
+                        lab[q] = 1;
+                        stack[top++] = q;
+                    }
+                }
+        }
+        if ((int64_t)cnt >= min_area)
+            for (size_t k = 0; k < cnt; ++k) out[members[k]] = 1;
+    }
+    free(lab);
+    free(stack);
+    free(members);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole path                                                                */
 /* ------------------------------------------------------------------------ */
 

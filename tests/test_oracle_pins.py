@@ -351,3 +351,52 @@ def test_ensemble_is_union_of_recent_masks():
             ref = np.logical_or.reduce(masks[max(0, t - k):t + 1]).astype(np.uint8)
             np.testing.assert_array_equal(out[t], ref)
     assert all(np.array_equal(a, b) for a, b in zip(oracle.ensemble(masks, 0), masks))
+
+
+# --------------------------------------------------------------------------- the paper's RoI rule
+
+def test_open_close_matches_scipy():
+    from scipy import ndimage
+    pre = (np.random.default_rng(31).uniform(size=(40, 37)) > 0.55).astype(np.uint8)
+    for r in (1, 2):
+        se = np.ones((2 * r + 1, 2 * r + 1), bool)
+        ero = lambda m: ndimage.binary_erosion(m, se, border_value=1)
+        dil = lambda m: ndimage.binary_dilation(m, se, border_value=0)
+        ref = ero(dil(dil(ero(pre.astype(bool))))).astype(np.uint8)
+        np.testing.assert_array_equal(oracle.open_close(pre, r), ref)
+
+
+def test_cc_filter_matches_scipy_label():
+    from scipy import ndimage
+    m = (np.random.default_rng(32).uniform(size=(50, 45)) > 0.6).astype(np.uint8)
+    lab, n = ndimage.label(m, structure=np.ones((3, 3)))
+    area = np.bincount(lab.ravel())
+    for a in (1, 3, 10, 40):
+        keep = area >= a
+        keep[0] = False
+        np.testing.assert_array_equal(oracle.cc_filter(m, a), keep[lab].astype(np.uint8))
+
+
+def test_saliency_bruteforce_and_closed_form():
+    rng = np.random.default_rng(33)
+    fl = rng.normal(size=(17, 23, 2))
+    M = np.hypot(fl[..., 0], fl[..., 1])
+    P = np.pad(M, 1, mode="edge")
+    G = np.hypot(0.5 * (P[1:-1, 2:] - P[1:-1, :-2]), 0.5 * (P[2:, 1:-1] - P[:-2, 1:-1]))
+    S = 0.7 * M / M.max() + 0.3 * G / G.max()
+    np.testing.assert_allclose(oracle.saliency(fl, 0.7), S / S.max(), atol=1e-14)
+    # uniform motion: no gradient, saliency 1 everywhere; no motion: 0
+    np.testing.assert_array_equal(oracle.saliency(np.ones((5, 6, 2)), 0.7), np.ones((5, 6)))
+    np.testing.assert_array_equal(oracle.saliency(np.zeros((5, 6, 2)), 0.7), np.zeros((5, 6)))
+    # magnitude growing linearly along x (interior): constant gradient term
+    xx = np.tile(np.arange(1.0, 11.0), (4, 1))
+    s = oracle.saliency(np.stack([xx, np.zeros_like(xx)], -1), 1.0)
+    np.testing.assert_allclose(s, xx / 10.0, atol=1e-15)
+
+
+def test_saliency_mask_top_fraction():
+    f0, f1, _ = synth.pair_512_u8(2)
+    fl = oracle.flow(f0[:128, :128].astype(float), f1[:128, :128].astype(float))
+    mask, s, tau = oracle.saliency_mask(fl, 1, 0.2)
+    assert (s > tau).sum() <= int(np.floor(0.2 * s.size))
+    assert mask.any() and mask.mean() < 0.6
