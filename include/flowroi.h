@@ -56,6 +56,22 @@ enum {
 };
 
 enum {
+    /* Mask rule. MAGNITUDE: pre = [|d| above the threshold]. SALIENCY
+     * (Method, Region of Interest extraction): motion saliency S combines
+     * the flow magnitude M = |d| with its spatial gradient G = |grad M|
+     * (central differences, replicated edges) with weight sal_weight on M,
+     * each term divided by its maximum over the frame, and S divided by its
+     * own maximum (the normalisation); pre = [S above the threshold] (TOP:
+     * the top `thresh` fraction of S, as the paper's RoI threshold of 0.2
+     * keeps the top 20 %; ABS: normalised S > thresh), then opening and
+     * closing with the (2 morph_radius + 1)^2 square, then removal of the
+     * 8-connected components smaller than min_area pixels. Both rules end
+     * with the dilation (dilate_radius, se_shape). */
+    ROI_RULE_MAGNITUDE = 0,
+    ROI_RULE_SALIENCY = 1
+};
+
+enum {
     ROI_SE_SQUARE = 0,       /* (2r+1)^2 square */
     ROI_SE_DISC = 1          /* offsets with u^2 + v^2 <= r^2 */
 };
@@ -94,12 +110,20 @@ typedef struct roi_params {
      * contexts only: the mask of frame t becomes the union of its own mask
      * and those of the previous `adjacent` frames of the stream. 0..8. */
     int32_t adjacent;
+    /* Mask rule (ROI_RULE_*). Under ROI_RULE_SALIENCY, thresh applies to
+     * the saliency: TOP fraction in (0, 1), or ABS level on the normalised
+     * saliency (>= 0). */
+    int32_t rule;
+    float sal_weight;      /* weight of the magnitude term, [0, 1] (the paper's 0.7) */
+    int32_t morph_radius;  /* opening/closing square radius, 0..2 (0 skips them) */
+    int32_t min_area;      /* smallest kept component, pixels, >= 0 (0 or 1 keeps all) */
 } roi_params;
 
 /* Defaults: levels 3, winsize 15, iterations 3, poly_n 5, poly_sigma 1.1,
  * eps 1e-3, ABS threshold 1.0 px, square dilation of radius 2, no flags,
  * denoising off (when on: 3x3 median, 5x5 bilateral, sigma_space 1.5,
- * sigma_range 20). */
+ * sigma_range 20), adjacent 0, magnitude rule (saliency rule settings:
+ * sal_weight 0.7, morph_radius 1, min_area 32). */
 void roi_default_params(roi_params *p);
 
 /* Host-only check of a request (no device work). ROI_OK, ROI_EINVAL for a
@@ -127,8 +151,30 @@ roi_status roi_mask(const void *prev, const void *next, int32_t h, int32_t w, in
 /* Squared threshold tau^2 that the last roi_mask / roi_mask_batched call on
  * this workspace applied (ABS: thresh^2; TOP: the (k+1)-th largest |d|^2
  * with k = floor(q h w)), copied to the host after synchronising `stream`.
- * For a batched call, `index` selects the pair. */
+ * For a batched call, `index` selects the pair. Under the saliency rule
+ * with TOP it is the (k+1)-th largest saliency before normalisation (S,
+ * not squared); under the saliency rule with ABS it is 0. */
 roi_status roi_read_tau2(const void *ws, int32_t index, float *tau2_out, void *stream);
+
+/* Workspace bytes roi_mask_from_flow needs (0 if the parameters fail the
+ * checks of roi_validate that concern the mask stage). */
+size_t roi_flow_mask_workspace_size(int32_t h, int32_t w, const roi_params *p);
+
+/* The mask stage alone, on a given flow field: the rule p->rule with its
+ * threshold, then the dilation, exactly as roi_mask applies them after its
+ * last update (the same kernels and per-pixel arithmetic, so a flow from
+ * roi_mask gives back roi_mask's mask).
+ *   flow      device, h*w*2 floats (pitch w), input.
+ *   mask      device, h*w uint8, output.
+ *   saliency  device, h*w floats (pitch w), output of the normalised
+ *             saliency under ROI_RULE_SALIENCY; may be NULL; ignored under
+ *             ROI_RULE_MAGNITUDE.
+ *   ws        device workspace of ws_bytes >= roi_flow_mask_workspace_size,
+ *             256-byte aligned; roi_read_tau2(ws, 0, ...) reads its threshold.
+ * Only the mask-stage fields of p are used (thresh_mode, thresh,
+ * dilate_radius, se_shape, rule, sal_weight, morph_radius, min_area). */
+roi_status roi_mask_from_flow(const float *flow, int32_t h, int32_t w, const roi_params *p, uint8_t *mask,
+                              float *saliency, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- Single steps, for testing each step in isolation ------------------ */
 

@@ -64,6 +64,8 @@ struct Plan {
     size_t init_off;  // coarsest-level initial flow
     size_t m2_off;    // |d|^2 at full resolution, pitch lv[0].pitch
     size_t hist_off;  // radix-select histogram
+    size_t area_off;  // component areas (h w int32), saliency rule only
+    size_t max_off;   // saliency maxima counters, saliency rule only
     size_t bytes;
 };
 
@@ -102,7 +104,9 @@ Plan make_plan(int h, int w, const roi_params *p)
     const Level &c = pl.lv[pl.L - 1];
     pl.init_off = take((size_t)c.h * c.pitch * sizeof(float2));
     pl.m2_off = take((size_t)pl.lv[0].h * pl.lv[0].pitch * sizeof(float));
-    pl.hist_off = take(SEL_BINS * sizeof(uint32_t));
+    pl.hist_off = take(SEL_COPIES * SEL_BINS * sizeof(uint32_t));
+    pl.area_off = p->rule == ROI_RULE_SALIENCY ? take((size_t)h * w * sizeof(int32_t)) : 0;
+    pl.max_off = p->rule == ROI_RULE_SALIENCY ? take(3 * MAXSLOT_WORDS * sizeof(uint32_t)) : 0;
     pl.bytes = off;
     return pl;
 }
@@ -481,6 +485,136 @@ roi_status launch_iter(const IterArgs &a, bool fp16, hipStream_t s)
 
 // Coarse-to-fine iterations from expansion set `s1` (prev) to `s2` (next),
 // then the threshold and dilation into `mask` (skipped when mask is NULL).
+// Buffers of the stage from |d|^2 to the mask. m2 (pitch m2_pitch) holds
+// |d|^2; under the saliency rule sal (h rows of sal_pitch floats), lab and
+// area (h w int32 each) are scratch, and the component links reuse m2.
+struct MaskBufs {
+    float *m2;
+    int m2_pitch;
+    uint32_t *hist;
+    float *sal;
+    int sal_pitch;
+    int32_t *lab;
+    int32_t *area;
+    uint32_t *maxs; // 3 MAXSLOT_WORDS counters: max M, max G, max S
+};
+
+void launch_select(const float *v, int pitch, int h, int w, const roi_params *p, SelState *slot, uint32_t *hist,
+                   hipStream_t s)
+{
+    const size_t N = (size_t)h * w;
+    const uint32_t rank = (uint32_t)std::floor((double)p->thresh * (double)N);
+    hipLaunchKernelGGL(k_sel_init, dim3(8), dim3(256), 0, s, slot, hist, rank, 0u, (uint32_t *)nullptr);
+    const dim3 g((w + 1023) / 1024, (h + 3) / 4);
+    hipLaunchKernelGGL(k_sel_hist, g, dim3(256), 0, s, v, pitch, h, w, (const SelState *)slot, hist, 0);
+    hipLaunchKernelGGL(k_sel_pick<0>, dim3(1), dim3(256), 0, s, slot, hist);
+    hipLaunchKernelGGL(k_sel_hist, g, dim3(256), 0, s, v, pitch, h, w, (const SelState *)slot, hist, 1);
+    hipLaunchKernelGGL(k_sel_pick<1>, dim3(1), dim3(256), 0, s, slot, hist);
+    hipLaunchKernelGGL(k_sel_hist, g, dim3(256), 0, s, v, pitch, h, w, (const SelState *)slot, hist, 2);
+    hipLaunchKernelGGL(k_sel_pick<2>, dim3(1), dim3(256), 0, s, slot, hist);
+}
+
+// Threshold (on |d| or, under the saliency rule, on the saliency after
+// opening/closing and small-component removal) and dilation into mask.
+// sal_out (nullable, pitch w) receives the normalised saliency.
+roi_status enqueue_mask(const MaskBufs &mb, SelState *slot, int h, int w, const roi_params *p, uint8_t *mask,
+                        float *sal_out, hipStream_t s)
+{
+    DilArgs d{};
+    d.m2 = mb.m2;
+    d.m2_pitch = mb.m2_pitch;
+    d.st = slot;
+    if (p->rule == ROI_RULE_MAGNITUDE) {
+        if (p->thresh_mode == ROI_THRESH_ABS) {
+            const float t2 = p->thresh * p->thresh;
+            uint32_t bits;
+            std::memcpy(&bits, &t2, 4);
+            hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, slot, mb.hist, 0u, bits, (uint32_t *)nullptr);
+        } else {
+            launch_select(mb.m2, mb.m2_pitch, h, w, p, slot, mb.hist, s);
+        }
+        LAUNCH_CHECK();
+    } else {
+        hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, slot, mb.hist, 0u, 0u, mb.maxs);
+        SalArgs a{};
+        a.m2 = mb.m2;
+        a.m2_pitch = mb.m2_pitch;
+        a.sal = mb.sal;
+        a.sal_pitch = mb.sal_pitch;
+        a.out = sal_out;
+        a.out_pitch = w;
+        a.maxs = mb.maxs;
+        a.h = h;
+        a.w = w;
+        a.wt = p->sal_weight;
+        const dim3 gs((w + SAL_TW - 1) / SAL_TW, (h + SAL_TH - 1) / SAL_TH), g4((w + 63) / 64, (h + 3) / 4);
+        hipLaunchKernelGGL(k_sal_max, gs, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_sal, gs, dim3(256), 0, s, a);
+        if (sal_out) hipLaunchKernelGGL(k_sal_norm, g4, dim3(256), 0, s, a);
+        // the selection runs on S before normalisation: dividing by max S
+        // keeps the order, so the same pixels are above the threshold
+        if (p->thresh_mode == ROI_THRESH_TOP) launch_select(mb.sal, mb.sal_pitch, h, w, p, slot, mb.hist, s);
+        const bool cc = p->min_area > 1;
+        MorphArgs m{};
+        m.sal = mb.sal;
+        m.sal_pitch = mb.sal_pitch;
+        m.st = slot;
+        m.maxs_S = mb.maxs + 2 * MAXSLOT_WORDS;
+        m.top = p->thresh_mode == ROI_THRESH_TOP;
+        m.thresh = p->thresh;
+        m.h = h;
+        m.w = w;
+        m.r = p->morph_radius;
+        m.lab = cc ? mb.lab : nullptr;
+        m.link = cc ? (int32_t *)mb.m2 : nullptr; // |d|^2 is no longer read
+        m.area = cc ? mb.area : nullptr;
+        // without the component stage the opened/closed mask goes to the lab
+        // buffer's bytes (other tiles are still reading S from sal)
+        m.pre = cc ? nullptr : (uint8_t *)mb.lab;
+        const dim3 gt((w + MO_TW - 1) / MO_TW, (h + MO_TH - 1) / MO_TH);
+        if (m.r == 0)
+            hipLaunchKernelGGL(k_open_close<0>, gt, dim3(256), 0, s, m);
+        else if (m.r == 1)
+            hipLaunchKernelGGL(k_open_close<1>, gt, dim3(256), 0, s, m);
+        else
+            hipLaunchKernelGGL(k_open_close<2>, gt, dim3(256), 0, s, m);
+        if (cc) {
+            hipLaunchKernelGGL(k_cc_border, gt, dim3(128), 0, s, (const int32_t *)mb.lab, m.link, h, w);
+            hipLaunchKernelGGL(k_cc_compress, gt, dim3(256), 0, s, mb.lab, m.link, mb.area, h, w);
+            d.lab = mb.lab;
+            d.area = mb.area;
+            d.min_area = p->min_area;
+        } else {
+            d.pre8 = (const uint8_t *)mb.lab;
+        }
+        LAUNCH_CHECK();
+    }
+    d.mask = mask;
+    d.mask_pitch = w;
+    d.h = h;
+    d.w = w;
+    d.r = p->dilate_radius;
+    for (int u = -d.r; u <= d.r; ++u) {
+        int hw = d.r;
+        if (p->se_shape == ROI_SE_DISC) {
+            hw = 0;
+            while ((hw + 1) * (hw + 1) + u * u <= d.r * d.r) ++hw;
+        }
+        d.hw[u + d.r] = (int8_t)hw;
+    }
+    dim3 g((w + DIL_TW - 1) / DIL_TW, (h + DIL_TH - 1) / DIL_TH);
+    switch (d.r) {
+    case 0: hipLaunchKernelGGL(k_dilate<0>, g, dim3(256), 0, s, d); break;
+    case 1: hipLaunchKernelGGL(k_dilate<1>, g, dim3(256), 0, s, d); break;
+    case 2: hipLaunchKernelGGL(k_dilate<2>, g, dim3(256), 0, s, d); break;
+    case 3: hipLaunchKernelGGL(k_dilate<3>, g, dim3(256), 0, s, d); break;
+    case 4: hipLaunchKernelGGL(k_dilate<4>, g, dim3(256), 0, s, d); break;
+    default: hipLaunchKernelGGL(k_dilate<-1>, g, dim3(256), 0, s, d); break;
+    }
+    LAUNCH_CHECK();
+    return ROI_OK;
+}
+
 roi_status enqueue_flow(const Plan &pl, uint8_t *base, SelState *slot, int s1, int s2, int h, int w,
                         const roi_params *p, float *flow, uint8_t *mask, hipStream_t s)
 {
@@ -557,49 +691,18 @@ roi_status enqueue_flow(const Plan &pl, uint8_t *base, SelState *slot, int s1, i
         wc = v.w;
     }
     if (!mask) return ROI_OK;
-    const float *m2 = (const float *)(base + pl.m2_off);
-    uint32_t *hist = (uint32_t *)(base + pl.hist_off);
-    const size_t N = (size_t)h * w;
-    if (p->thresh_mode == ROI_THRESH_ABS) {
-        const float t2 = p->thresh * p->thresh;
-        uint32_t bits;
-        std::memcpy(&bits, &t2, 4);
-        hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, slot, hist, 0u, bits);
-        LAUNCH_CHECK();
-    } else {
-        const uint32_t rank = (uint32_t)std::floor((double)p->thresh * (double)N);
-        hipLaunchKernelGGL(k_sel_init, dim3(8), dim3(256), 0, s, slot, hist, rank, 0u);
-        LAUNCH_CHECK();
-        const int blocks = (int)std::min<size_t>((N + 255) / 256, 1024);
-        for (int pass = 0; pass < 3; ++pass) {
-            hipLaunchKernelGGL(k_sel_hist, dim3(blocks), dim3(256), 0, s, m2, pl.lv[0].pitch, h, w,
-                               (const SelState *)slot, hist, pass);
-            LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, slot, hist, pass);
-            LAUNCH_CHECK();
-        }
-    }
-    DilArgs d{};
-    d.m2 = m2;
-    d.m2_pitch = pl.lv[0].pitch;
-    d.st = slot;
-    d.mask = mask;
-    d.mask_pitch = w;
-    d.h = h;
-    d.w = w;
-    d.r = p->dilate_radius;
-    for (int u = -d.r; u <= d.r; ++u) {
-        int hw = d.r;
-        if (p->se_shape == ROI_SE_DISC) {
-            hw = 0;
-            while ((hw + 1) * (hw + 1) + u * u <= d.r * d.r) ++hw;
-        }
-        d.hw[u + d.r] = (int8_t)hw;
-    }
-    dim3 g((w + DIL_TW - 1) / DIL_TW, (h + DIL_TH - 1) / DIL_TH);
-    hipLaunchKernelGGL(k_dilate, g, dim3(256), 0, s, d);
-    LAUNCH_CHECK();
-    return ROI_OK;
+    MaskBufs mb{};
+    mb.m2 = (float *)(base + pl.m2_off);
+    mb.m2_pitch = pl.lv[0].pitch;
+    mb.hist = (uint32_t *)(base + pl.hist_off);
+    // the saliency rule's buffers reuse the level-0 flow scratch, free once
+    // the last update has written the caller's flow
+    mb.sal = (float *)(base + pl.lv[0].fa);
+    mb.sal_pitch = pl.lv[0].pitch;
+    mb.lab = (int32_t *)(base + pl.lv[0].fa + (size_t)pl.lv[0].h * pl.lv[0].pitch * sizeof(float));
+    mb.area = (int32_t *)(base + pl.area_off);
+    mb.maxs = (uint32_t *)(base + pl.max_off);
+    return enqueue_mask(mb, slot, h, w, p, mask, nullptr, s);
 }
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
@@ -668,6 +771,32 @@ void roi_default_params(roi_params *p)
     p->sigma_space = 1.5f;
     p->sigma_range = 20.0f;
     p->adjacent = 0;
+    p->rule = ROI_RULE_MAGNITUDE;
+    p->sal_weight = 0.7f;
+    p->morph_radius = 1;
+    p->min_area = 32;
+}
+
+// checks of the fields the mask stage reads
+roi_status validate_mask_stage(const roi_params *p)
+{
+    if (p->rule != ROI_RULE_MAGNITUDE && p->rule != ROI_RULE_SALIENCY) return ROI_EINVAL;
+    if (p->thresh_mode == ROI_THRESH_ABS) {
+        if (!std::isfinite(p->thresh) || p->thresh < 0.0f) return ROI_EINVAL;
+    } else if (p->thresh_mode == ROI_THRESH_TOP) {
+        if (!(p->thresh > 0.0f && p->thresh < 1.0f)) return ROI_EINVAL;
+    } else {
+        return ROI_EINVAL;
+    }
+    if (p->dilate_radius < 0) return ROI_EINVAL;
+    if (p->se_shape != ROI_SE_SQUARE && p->se_shape != ROI_SE_DISC) return ROI_EINVAL;
+    if (p->dilate_radius > DIL_MAXR) return ROI_EUNSUPPORTED;
+    if (p->rule == ROI_RULE_SALIENCY) {
+        if (!(p->sal_weight >= 0.0f && p->sal_weight <= 1.0f)) return ROI_EINVAL;
+        if (p->morph_radius < 0 || p->min_area < 0) return ROI_EINVAL;
+        if (p->morph_radius > MO_MAXR) return ROI_EUNSUPPORTED;
+    }
+    return ROI_OK;
 }
 
 roi_status roi_validate(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p)
@@ -679,15 +808,8 @@ roi_status roi_validate(int32_t h, int32_t w, roi_dtype dtype, const roi_params 
     if (p->iterations < 1 || p->iterations > 64) return ROI_EINVAL;
     if (p->poly_n != 3 && p->poly_n != 5 && p->poly_n != 7) return ROI_EINVAL;
     if (!finite_pos(p->poly_sigma) || !finite_pos(p->eps)) return ROI_EINVAL;
-    if (p->thresh_mode == ROI_THRESH_ABS) {
-        if (!std::isfinite(p->thresh) || p->thresh < 0.0f) return ROI_EINVAL;
-    } else if (p->thresh_mode == ROI_THRESH_TOP) {
-        if (!(p->thresh > 0.0f && p->thresh < 1.0f)) return ROI_EINVAL;
-    } else {
-        return ROI_EINVAL;
-    }
-    if (p->dilate_radius < 0) return ROI_EINVAL;
-    if (p->se_shape != ROI_SE_SQUARE && p->se_shape != ROI_SE_DISC) return ROI_EINVAL;
+    const roi_status ms = validate_mask_stage(p);
+    if (ms == ROI_EINVAL) return ms;
     if (p->flags & ~(uint32_t)(ROI_USE_INITIAL_FLOW | ROI_FP16_STORAGE)) return ROI_EINVAL;
     if (p->denoise != 0 && p->denoise != 1) return ROI_EINVAL;
     if (p->adjacent < 0) return ROI_EINVAL;
@@ -698,7 +820,7 @@ roi_status roi_validate(int32_t h, int32_t w, roi_dtype dtype, const roi_params 
         if (p->median_radius > DN_MAXM || p->bilateral_radius > DN_MAXB) return ROI_EUNSUPPORTED;
     }
     if (p->winsize > 2 * IT_MAXR + 1) return ROI_EUNSUPPORTED;
-    if (p->dilate_radius > DIL_MAXR) return ROI_EUNSUPPORTED;
+    if (ms != ROI_OK) return ms;
     if (h > 32768 || w > 32768) return ROI_EUNSUPPORTED;
     // the iteration kernel addresses a level's packed plane (16 B per pixel
     // of a 64-aligned row) with 32-bit byte offsets
@@ -741,6 +863,64 @@ roi_status roi_read_tau2(const void *ws, int32_t index, float *tau2_out, void *s
         return ROI_EDEVICE;
     std::memcpy(tau2_out, &sst.tau2_bits, 4);
     return ROI_OK;
+}
+
+// Workspace of roi_mask_from_flow after the header: m2 and sal (h rows of a
+// 64-aligned pitch each), lab and area (h w int32 each), the select
+// histogram, the saliency maxima counters.
+struct FlowMaskPlan {
+    int pitch;
+    size_t m2, sal, lab, area, hist, maxs, bytes;
+};
+
+FlowMaskPlan flow_mask_plan(int h, int w)
+{
+    FlowMaskPlan f{};
+    f.pitch = (int)align_up((size_t)w, 64);
+    const size_t plane = align_up((size_t)h * f.pitch * sizeof(float), ALIGN);
+    f.m2 = 0;
+    f.sal = plane;
+    f.lab = 2 * plane;
+    f.area = f.lab + align_up((size_t)h * w * sizeof(int32_t), ALIGN);
+    f.hist = f.area + align_up((size_t)h * w * sizeof(int32_t), ALIGN);
+    f.maxs = f.hist + align_up(SEL_COPIES * SEL_BINS * sizeof(uint32_t), ALIGN);
+    f.bytes = f.maxs + 3 * MAXSLOT_WORDS * sizeof(uint32_t);
+    return f;
+}
+
+size_t roi_flow_mask_workspace_size(int32_t h, int32_t w, const roi_params *p)
+{
+    if (!p || h < 0 || w < 0 || h > 32768 || w > 32768 || validate_mask_stage(p) != ROI_OK) return 0;
+    if (h == 0 || w == 0) return HDR_BYTES;
+    return HDR_BYTES + flow_mask_plan(h, w).bytes;
+}
+
+roi_status roi_mask_from_flow(const float *flow, int32_t h, int32_t w, const roi_params *p, uint8_t *mask,
+                              float *saliency, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!p || h < 0 || w < 0) return ROI_EINVAL;
+    roi_status st = validate_mask_stage(p);
+    if (st != ROI_OK) return st;
+    if (h > 32768 || w > 32768) return ROI_EUNSUPPORTED;
+    if (h == 0 || w == 0) return ROI_OK;
+    if (!flow || !mask || !ws || (uintptr_t)ws % ALIGN) return ROI_EINVAL;
+    const FlowMaskPlan f = flow_mask_plan(h, w);
+    if (ws_bytes < HDR_BYTES + f.bytes) return ROI_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *base = (uint8_t *)ws + HDR_BYTES;
+    MaskBufs mb{};
+    mb.m2 = (float *)(base + f.m2);
+    mb.m2_pitch = f.pitch;
+    mb.sal = (float *)(base + f.sal);
+    mb.sal_pitch = f.pitch;
+    mb.lab = (int32_t *)(base + f.lab);
+    mb.area = (int32_t *)(base + f.area);
+    mb.maxs = (uint32_t *)(base + f.maxs);
+    mb.hist = (uint32_t *)(base + f.hist);
+    hipLaunchKernelGGL(k_mag2, dim3((w + 63) / 64, (h + 3) / 4), dim3(256), 0, s, (const float2 *)flow, h, w, mb.m2,
+                       f.pitch);
+    LAUNCH_CHECK();
+    return enqueue_mask(mb, (SelState *)ws, h, w, p, mask, p->rule == ROI_RULE_SALIENCY ? saliency : nullptr, s);
 }
 
 roi_status roi_pyr_down(const float *src, int32_t h, int32_t w, float *dst, void *stream)

@@ -8,12 +8,19 @@
 //                2x-upsampled coarser flow), bilinear warp of next's
 //                coefficients, per-pixel normal equations, box pooling,
 //                regularised 2x2 solve, optional |d|^2 epilogue
-//   k_hist/k_pick radix select of the top-q threshold on |d|^2 bit patterns
+//   k_sel_hist   radix select of the top-q threshold on float bit patterns
+//                (|d|^2, or the saliency), the pick fused into the last block
 //   k_dilate     threshold + binary dilation into the RoI mask
+// Denoising pre-stage (k_denoise: median then bilateral), the saliency rule
+// (k_sal_max, k_sal: motion saliency from |d| and its gradient; k_open_close:
+// threshold, opening, closing and tile-local component labels; k_cc_border,
+// k_cc_compress: components across tiles and their areas) and the
+// adjacent-frame ensemble (k_ensemble) complete the set.
 //
-// Every kernel is a plain grid over output tiles staged through LDS; all
-// arithmetic is FP32 (storage may be FP16). Border handling replicates the
-// edge pixel for stencils and warps; the dilation treats outside as 0.
+// Every kernel is a plain grid over output tiles staged through LDS. Pyramid
+// and expansion arithmetic is FP64 (storage FP32, or FP16 for the
+// expansions), the rest FP32. Border handling replicates the edge pixel for
+// stencils and warps; the dilation treats outside as 0.
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -394,6 +401,9 @@ constexpr int IT_TW = 64, IT_MAXR = 7;
 
 enum { PRIOR_ZERO = 0, PRIOR_PLAIN = 1, PRIOR_UPSAMPLE = 2 };
 
+// |d|^2 as every kernel that thresholds or weights the flow magnitude computes it
+__device__ __forceinline__ float mag2(float2 d) { return __fmaf_rn(d.x, d.x, d.y * d.y); }
+
 struct IterArgs {
     const void *p4[2], *p1[2]; // packed expansions of prev [0] and next [1]
     int32_t rpitch;            // pixels per row of the packed planes
@@ -655,7 +665,7 @@ __device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs,
             const float2 d = solve2(vv[0], vv[IT_CH * IT_TW], vv[2 * IT_CH * IT_TW], vv[3 * IT_CH * IT_TW],
                                     vv[4 * IT_CH * IT_TW], a.eps);
             a.fout[(size_t)oy * a.fout_pitch + x] = d;
-            if (a.m2) a.m2[(size_t)oy * a.m2_pitch + x] = d.x * d.x + d.y * d.y;
+            if (a.m2) a.m2[(size_t)oy * a.m2_pitch + x] = mag2(d);
         }
     }
     // no barrier: vs is next written by 3a of a later chunk, two barriers away
@@ -724,10 +734,25 @@ constexpr int SEL_BINS = 2048;
 
 struct SelState { uint32_t prefix, rank, tau2_bits, pad; };
 
+// The global histogram is kept in SEL_COPIES copies, block b adding into
+// copy b mod SEL_COPIES, so that a bin's atomics from a thousand blocks
+// spread over several addresses; the pick sums the copies.
+constexpr int SEL_COPIES = 8;
+
+// Frame maxima of the saliency rule (max |d|, max |grad |d||, max S): each
+// is kept in MAXSLOTS counters 256 bytes apart, block b raising counter
+// b mod MAXSLOTS, so that the atomics of thousands of blocks spread over
+// the L2 channels instead of queueing on one address; readers reduce the
+// counters with one load per lane of a wave.
+constexpr int MAXSLOTS = 64, MAXSLOT_STRIDE = 64, MAXSLOT_WORDS = MAXSLOTS * MAXSLOT_STRIDE;
+
 __host__ __device__ constexpr int sel_shift(int pass) { return pass == 0 ? 21 : (pass == 1 ? 10 : 0); }
 __host__ __device__ constexpr int sel_bits(int pass) { return pass == 2 ? 10 : 11; }
 
-__global__ __launch_bounds__(256) void k_sel_init(SelState *st, uint32_t *hist, uint32_t rank, uint32_t tau2_bits)
+// maxs (nullable): 3 MAXSLOT_WORDS counter groups to clear
+// hist: SEL_COPIES * SEL_BINS counters
+__global__ __launch_bounds__(256) void k_sel_init(SelState *st, uint32_t *hist, uint32_t rank, uint32_t tau2_bits,
+                                                  uint32_t *maxs)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->prefix = 0;
@@ -735,58 +760,104 @@ __global__ __launch_bounds__(256) void k_sel_init(SelState *st, uint32_t *hist, 
         st->tau2_bits = tau2_bits;
         st->pad = 0;
     }
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < SEL_BINS; i += gridDim.x * 256) hist[i] = 0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < SEL_COPIES * SEL_BINS; i += gridDim.x * 256) hist[i] = 0;
+    if (maxs && blockIdx.x == 0 && threadIdx.x < 3 * MAXSLOTS) maxs[threadIdx.x * MAXSLOT_STRIDE] = 0;
 }
 
+// One histogram pass: the next digit of the values that share the prefix
+// found so far. Thread (tx, ty) of block (bx, by) reads 16 consecutive
+// values of row 4 by + ty from column 16 (64 bx + tx) with all four loads in
+// flight together (rows start 64-byte aligned: the pitch is a multiple of
+// 64), and merges runs of equal bins before its LDS atomic, which matters
+// for smooth fields whose neighbours share the top bits.
+// grid: (ceil(w/1024), ceil(h/4)), 256 threads
 __global__ __launch_bounds__(256) void k_sel_hist(const float *m2, int32_t pitch, int32_t h, int32_t w,
                                                   const SelState *st, uint32_t *hist, int32_t pass)
 {
     __shared__ uint32_t lh[SEL_BINS];
     for (int i = threadIdx.x; i < SEL_BINS; i += 256) lh[i] = 0;
-    __syncthreads();
     const int shift = sel_shift(pass), nb = 1 << sel_bits(pass);
     const uint32_t prefix = st->prefix;
     const int hi = shift + sel_bits(pass);
-    const size_t n = (size_t)h * w;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-        const size_t y = i / w, x = i - y * w;
-        const uint32_t v = __float_as_uint(m2[y * pitch + x]);
-        if (pass > 0 && (v >> hi) != prefix) continue;
-        atomicAdd(&lh[(v >> shift) & (nb - 1)], 1u);
+    const int tx = threadIdx.x & 63, y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int x0 = (blockIdx.x * 64 + tx) * 16;
+    const int n = y < h ? max(0, min(16, w - x0)) : 0;
+    uint32_t v[16];
+    const float *row = m2 + (size_t)min(y, h - 1) * pitch;
+    if (n == 16) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float4 q = *(const float4 *)(row + x0 + 4 * k);
+            v[4 * k] = __float_as_uint(q.x);
+            v[4 * k + 1] = __float_as_uint(q.y);
+            v[4 * k + 2] = __float_as_uint(q.z);
+            v[4 * k + 3] = __float_as_uint(q.w);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = k < n ? __float_as_uint(row[x0 + k]) : 0u;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nb; i += 256)
-        if (lh[i]) atomicAdd(&hist[i], lh[i]);
-}
-
-// one block of 256 threads; each owns 8 consecutive bins
-__global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, int32_t pass)
-{
-    __shared__ uint32_t part[256];
-    __shared__ uint32_t above[256];
-    const int nb = 1 << sel_bits(pass), per = nb / 256;
-    const int t = threadIdx.x;
-    // read the state before any thread can update it (updates follow the barriers)
-    const uint32_t rank = st->rank, prefix0 = st->prefix;
-    // thread t covers bins [nb - per (t+1), nb - per t): thread 0 holds the largest values
-    const int b_hi = nb - per * t - 1;
-    uint32_t cnt[8];
-    uint32_t sum = 0;
-    for (int j = 0; j < per; ++j) {
-        cnt[j] = hist[b_hi - j];
-        sum += cnt[j];
-    }
-    part[t] = sum;
-    __syncthreads();
-    if (t == 0) {
-        uint32_t acc = 0;
-        for (int i = 0; i < 256; ++i) {
-            above[i] = acc;
-            acc += part[i];
+    int cur = -1;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k >= n || (pass > 0 && (v[k] >> hi) != prefix)) continue;
+        const int bin = (int)((v[k] >> shift) & (uint32_t)(nb - 1));
+        if (bin == cur) {
+            ++cnt;
+        } else {
+            if (cnt) atomicAdd(&lh[cur], cnt);
+            cur = bin;
+            cnt = 1;
         }
     }
+    if (cnt) atomicAdd(&lh[cur], cnt);
     __syncthreads();
-    uint32_t acc = above[t];
+    uint32_t *hc = hist + (size_t)((blockIdx.y * gridDim.x + blockIdx.x) % SEL_COPIES) * SEL_BINS;
+    for (int i = threadIdx.x; i < nb; i += 256)
+        if (lh[i]) atomicAdd(&hc[i], lh[i]);
+}
+
+// Picks the bin holding the sought rank from the finished histogram of a
+// pass: thread t (of 256) covers bins [nb - per (t+1), nb - per t), so thread
+// 0 holds the largest values; an exclusive scan of the per-thread counts
+// (wave scans, then the four wave totals) gives each thread the number of
+// values above its bins. Clears the bins it read for the next pass.
+// grid: 1 block of 256 threads
+template <int PASS>
+__global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist)
+{
+    constexpr int pass = PASS, nb = 1 << sel_bits(PASS), per = nb / 256;
+    __shared__ uint32_t wsum[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint32_t rank = st->rank, prefix0 = st->prefix;
+    const int b_hi = nb - per * t - 1;
+    uint32_t cnt[per];
+    uint32_t sum = 0;
+    // all per * SEL_COPIES loads in flight together
+    uint32_t raw[per][SEL_COPIES];
+#pragma unroll
+    for (int j = 0; j < per; ++j)
+#pragma unroll
+        for (int k = 0; k < SEL_COPIES; ++k) raw[j][k] = hist[k * SEL_BINS + b_hi - j];
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < SEL_COPIES; ++k) c += raw[j][k];
+        cnt[j] = c;
+        sum += c;
+    }
+    uint32_t inc = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    uint32_t acc = inc - sum;
+    for (int k = 0; k < wv; ++k) acc += wsum[k];
     if (rank >= acc && rank < acc + sum) {
         for (int j = 0; j < per; ++j) {
             if (rank < acc + cnt[j]) {
@@ -799,17 +870,25 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, 
             acc += cnt[j];
         }
     }
-    __syncthreads();
-    for (int j = 0; j < per; ++j) hist[b_hi - j] = 0;
+#pragma unroll
+    for (int j = 0; j < per; ++j)
+#pragma unroll
+        for (int k = 0; k < SEL_COPIES; ++k) hist[k * SEL_BINS + b_hi - j] = 0;
 }
 
 // ---------------------------------------------------------------- threshold + dilation
 
-constexpr int DIL_TW = 64, DIL_TH = 16, DIL_MAXR = 32;
+constexpr int DIL_TW = 64, DIL_TH = 16, DIL_MAXR = 32, DIL_FASTR = 4;
+static_assert(DIL_TW == 64, "one wave spans a tile row");
 
 struct DilArgs {
     const float *m2; int32_t m2_pitch;
     const SelState *st;        // tau^2 bits live in st->tau2_bits
+    // alternative sources of pre (saliency rule): when lab is set, pre(p) =
+    // [lab(p) >= 0 and area(lab(p)) >= min_area]; else when pre8 is set,
+    // pre(p) = pre8(p); both pitch w
+    const int32_t *lab; const int32_t *area; int32_t min_area;
+    const uint8_t *pre8;
     uint8_t *mask; int32_t mask_pitch;
     int32_t h, w, r;
     int8_t hw[2 * DIL_MAXR + 1]; // half-width of the structuring element on row offset u
@@ -819,39 +898,561 @@ struct DilArgs {
 // outside the frame counting as 0. Row pass: distance to the nearest set
 // pixel within +-r on the same row; column pass: OR_u [dist(y+u) <= hw(u)].
 // grid: (ceil(w/64), ceil(h/16))
+// RF >= 0: the radius is RF (a.r == RF), so the tap loops unroll; RF < 0:
+// any radius up to DIL_MAXR.
+template <int RF>
 __global__ __launch_bounds__(256) void k_dilate(DilArgs a)
 {
     constexpr int SW = DIL_TW + 2 * DIL_MAXR, SH = DIL_TH + 2 * DIL_MAXR;
     __shared__ uint8_t pre[SH][SW];
     __shared__ uint8_t dist[SH][DIL_TW];
-    const int r = a.r, sw = DIL_TW + 2 * r, sh = DIL_TH + 2 * r;
+    const int r = RF >= 0 ? RF : a.r, sw = DIL_TW + 2 * r, sh = DIL_TH + 2 * r;
     const int ox0 = blockIdx.x * DIL_TW, oy0 = blockIdx.y * DIL_TH;
-    const uint32_t t2 = a.st->tau2_bits;
-    for (int i = threadIdx.x; i < sh * sw; i += 256) {
-        const int rr = i / sw, c = i - rr * sw;
+    const uint32_t t2 = a.lab || a.pre8 ? 0u : a.st->tau2_bits;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    auto pre_at = [&](int rr, int c) -> uint8_t {
         const int y = oy0 - r + rr, x = ox0 - r + c;
-        uint8_t v = 0;
-        if (y >= 0 && y < a.h && x >= 0 && x < a.w)
-            v = __float_as_uint(a.m2[(size_t)y * a.m2_pitch + x]) > t2 ? 1 : 0;
-        pre[rr][c] = v;
+        if (y < 0 || y >= a.h || x < 0 || x >= a.w) return 0;
+        const size_t q = (size_t)y * a.w + x;
+        if (a.lab) {
+            const int32_t l = a.lab[q];
+            return l >= 0 && a.area[l] >= a.min_area ? 1 : 0;
+        }
+        if (a.pre8) return a.pre8[q];
+        return __float_as_uint(a.m2[(size_t)y * a.m2_pitch + x]) > t2 ? 1 : 0;
+    };
+    if (r <= DIL_FASTR) {
+        // small radius: every load of the thread is issued before the first
+        // LDS store (rows ty + 4k, columns tx and, in the right halo, tx + 64)
+        constexpr int LR = (DIL_TH + 2 * DIL_FASTR) / 4;
+        uint8_t v0[LR], v1[LR];
+#pragma unroll
+        for (int k = 0; k < LR; ++k) {
+            const int rr = ty + 4 * k;
+            v0[k] = rr < sh ? pre_at(rr, tx) : 0;
+            v1[k] = rr < sh && tx + 64 < sw ? pre_at(rr, tx + 64) : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < LR; ++k) {
+            const int rr = ty + 4 * k;
+            if (rr < sh) {
+                pre[rr][tx] = v0[k];
+                if (tx + 64 < sw) pre[rr][tx + 64] = v1[k];
+            }
+        }
+    } else {
+        for (int rr = ty; rr < sh; rr += 4)
+            for (int c = tx; c < sw; c += 64) pre[rr][c] = pre_at(rr, c);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < sh * DIL_TW; i += 256) {
-        const int rr = i / DIL_TW, c = i - rr * DIL_TW;
+    for (int rr = ty; rr < sh; rr += 4) {
+        const int c = tx;
         int d = r + 1;
+#pragma unroll
         for (int v = -r; v <= r; ++v)
             if (pre[rr][c + r + v]) d = min(d, abs(v));
         dist[rr][c] = (uint8_t)d;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < DIL_TH * DIL_TW; i += 256) {
-        const int rr = i / DIL_TW, c = i - rr * DIL_TW;
+    for (int rr = ty; rr < DIL_TH; rr += 4) {
+        const int c = tx;
         const int y = oy0 + rr, x = ox0 + c;
         if (y >= a.h || x >= a.w) continue;
         uint8_t m = 0;
+#pragma unroll
         for (int u = -r; u <= r; ++u) m |= dist[rr + r + u][c] <= a.hw[u + r] ? 1 : 0;
         a.mask[(size_t)y * a.mask_pitch + x] = m;
     }
+}
+
+// ---------------------------------------------------------------- saliency rule
+
+// |d|^2 of a flow field (pitch w, interleaved x/y) into m2 (pitch m2_pitch).
+// grid: (ceil(w/64), ceil(h/4)), 256 threads
+__global__ __launch_bounds__(256) void k_mag2(const float2 *flow, int32_t h, int32_t w, float *m2, int32_t m2_pitch)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x < w && y < h) m2[(size_t)y * m2_pitch + x] = mag2(flow[(size_t)y * w + x]);
+}
+
+constexpr int SAL_TW = 64, SAL_TH = 32; // one block: 64 x 32 pixels, 8 per thread
+
+struct SalArgs {
+    const float *m2; int32_t m2_pitch;
+    float *sal; int32_t sal_pitch; // S before normalisation by its maximum
+    float *out; int32_t out_pitch; // nullable: S / max S
+    uint32_t *maxs;                // counter groups of max M, max G, max S
+    int32_t h, w;
+    float wt;
+};
+
+// maximum of v over the block, then one atomic max per block into the
+// block's counter of the group (non-negative floats order like their bits)
+__device__ __forceinline__ void block_max_to(float v, uint32_t *group, float *red)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        const int slot = (int)((blockIdx.y * gridDim.x + blockIdx.x) % MAXSLOTS);
+        atomicMax(group + slot * MAXSLOT_STRIDE, __float_as_uint(m));
+    }
+}
+
+// the group's maximum, in every lane of the calling wave
+__device__ __forceinline__ float group_max(const uint32_t *group)
+{
+    float v = __uint_as_float(group[(threadIdx.x & 63) * MAXSLOT_STRIDE]);
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// M = |d| over the block's tile and a one-pixel halo, edges replicated
+// (coordinates clamped to the frame), into LDS; the hardware square root
+// (within 1 ulp). Every load of the thread is issued before the first LDS
+// store. Thread (tx, ty) of 64 x 4 fills rows ty + 4k, columns tx and 64 + tx.
+constexpr int SAL_LW = SAL_TW + 2, SAL_LH = SAL_TH + 2, SAL_LR = (SAL_LH + 3) / 4;
+
+__device__ __forceinline__ void stage_mag(const SalArgs &a, float (*Ms)[SAL_LW], int tx, int ty)
+{
+    const int x0 = blockIdx.x * SAL_TW - 1, y0 = blockIdx.y * SAL_TH - 1;
+    float v0[SAL_LR], v1[SAL_LR];
+    const int xa = min(max(x0 + tx, 0), a.w - 1), xb = min(x0 + 64 + tx, a.w - 1);
+#pragma unroll
+    for (int k = 0; k < SAL_LR; ++k) {
+        const int ly = min(ty + 4 * k, SAL_LH - 1);
+        const float *row = a.m2 + (size_t)min(max(y0 + ly, 0), a.h - 1) * a.m2_pitch;
+        v0[k] = row[xa];
+        v1[k] = row[xb];
+    }
+#pragma unroll
+    for (int k = 0; k < SAL_LR; ++k) {
+        const int ly = ty + 4 * k;
+        if (ly < SAL_LH) {
+            Ms[ly][tx] = __builtin_amdgcn_sqrtf(v0[k]);
+            if (tx < SAL_LW - 64) Ms[ly][64 + tx] = __builtin_amdgcn_sqrtf(v1[k]);
+        }
+    }
+    __syncthreads();
+}
+
+// G = |grad M| by central differences at tile pixel (ly, lx), whose LDS
+// cell is (ly + 1, lx + 1)
+__device__ __forceinline__ float grad_mag(const float (*Ms)[SAL_LW], int ly, int lx)
+{
+    const float gx = 0.5f * (Ms[ly + 1][lx + 2] - Ms[ly + 1][lx]);
+    const float gy = 0.5f * (Ms[ly + 2][lx + 1] - Ms[ly][lx + 1]);
+    return __builtin_amdgcn_sqrtf(__fmaf_rn(gx, gx, gy * gy));
+}
+
+// pass 1: max M and max G. grid: (ceil(w/64), ceil(h/32)), 256 threads
+__global__ __launch_bounds__(256) void k_sal_max(SalArgs a)
+{
+    __shared__ float Ms[SAL_LH][SAL_LW];
+    __shared__ float red[2][4];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    stage_mag(a, Ms, tx, ty);
+    const int x = blockIdx.x * SAL_TW + tx;
+    float mM = 0.0f, mG = 0.0f;
+#pragma unroll
+    for (int k = 0; k < SAL_TH / 4; ++k) {
+        const int ly = ty + 4 * k, y = blockIdx.y * SAL_TH + ly;
+        if (x < a.w && y < a.h) {
+            mM = fmaxf(mM, Ms[ly + 1][tx + 1]);
+            mG = fmaxf(mG, grad_mag(Ms, ly, tx));
+        }
+    }
+    block_max_to(mM, a.maxs, red[0]);
+    block_max_to(mG, a.maxs + MAXSLOT_WORDS, red[1]);
+}
+
+// pass 2: S = wt M / max M + (1 - wt) G / max G (a term with a zero maximum
+// contributes 0), stored before normalisation; max S. Same grid as pass 1.
+__global__ __launch_bounds__(256) void k_sal(SalArgs a)
+{
+    __shared__ float Ms[SAL_LH][SAL_LW];
+    __shared__ float red[4];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const float mM = group_max(a.maxs), mG = group_max(a.maxs + MAXSLOT_WORDS);
+    const float cM = mM > 0.0f ? a.wt / mM : 0.0f, cG = mG > 0.0f ? (1.0f - a.wt) / mG : 0.0f;
+    stage_mag(a, Ms, tx, ty);
+    const int x = blockIdx.x * SAL_TW + tx;
+    float mS = 0.0f;
+#pragma unroll
+    for (int k = 0; k < SAL_TH / 4; ++k) {
+        const int ly = ty + 4 * k, y = blockIdx.y * SAL_TH + ly;
+        if (x < a.w && y < a.h) {
+            const float S = __fmaf_rn(cM, Ms[ly + 1][tx + 1], cG * grad_mag(Ms, ly, tx));
+            a.sal[(size_t)y * a.sal_pitch + x] = S;
+            mS = fmaxf(mS, S);
+        }
+    }
+    block_max_to(mS, a.maxs + 2 * MAXSLOT_WORDS, red);
+}
+
+__device__ __forceinline__ float sal_norm(float S, float mS) { return mS > 0.0f ? S / mS : 0.0f; }
+
+// normalised saliency out. grid: (ceil(w/64), ceil(h/4)), 256 threads
+__global__ __launch_bounds__(256) void k_sal_norm(SalArgs a)
+{
+    const float mS = group_max(a.maxs + 2 * MAXSLOT_WORDS); // whole wave, before the bounds test
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x < a.w && y < a.h) a.out[(size_t)y * a.out_pitch + x] = sal_norm(a.sal[(size_t)y * a.sal_pitch + x], mS);
+}
+
+// Threshold, opening and closing with the (2r+1)^2 square, all in LDS.
+// Erosion takes the minimum and dilation the maximum over the part of the
+// square inside the frame (separably: rows, then columns). The four
+// operations widen the support by 4r, so a 64 x 32 tile loads a 4r halo.
+// With the component stage on, the kernel then labels the tile's
+// 8-connected components in LDS (the first pass of the labelling below).
+constexpr int MO_TW = 64, MO_TH = 32, MO_MAXR = 2, MO_HALO = 4 * MO_MAXR;
+static_assert(MO_TW == 64, "one wave spans a tile row; local indices split as (i >> 6, i & 63)");
+
+struct MorphArgs {
+    const float *sal; int32_t sal_pitch;
+    const SelState *st;
+    const uint32_t *maxs_S;  // counter group of max S
+    int32_t top;     // 1: pre = [S > tau] (tau bits in st->tau2_bits); 0: pre = [S / max S > thresh]
+    float thresh;
+    int32_t h, w, r;
+    // component stage (lab set): lab(p) = index y w + x of the smallest
+    // pixel of p's component within its tile (-1 background); at that pixel
+    // (the tile root) link(p) = p and area(p) = 0. All pitch-free h w int32.
+    int32_t *lab, *link, *area;
+    uint8_t *pre;    // without lab: the opened and closed mask (pitch w)
+};
+
+// Union-find on label links. Every link points to a smaller or equal index
+// (L[x] <= x) and links only decrease (atomic minimum), so a find walks a
+// strictly decreasing chain and a union retries with a strictly smaller
+// root each time it loses a race. Finds halve paths (x -> grandparent);
+// only roots are ever linked by a union, and a node that is not a root
+// never becomes one again, so halving never touches a root.
+template <int SCOPE>
+__device__ __forceinline__ int32_t uf_load(const int32_t *L, int32_t x)
+{
+    return __hip_atomic_load(L + x, __ATOMIC_RELAXED, SCOPE);
+}
+
+template <int SCOPE>
+__device__ __forceinline__ int32_t uf_find(int32_t *L, int32_t x)
+{
+    for (;;) {
+        const int32_t p = uf_load<SCOPE>(L, x);
+        if (p == x) return x;
+        const int32_t g = uf_load<SCOPE>(L, p);
+        if (g == p) return p;
+        atomicMin(L + x, g);
+        x = g;
+    }
+}
+
+template <int SCOPE>
+__device__ __forceinline__ void uf_union(int32_t *L, int32_t a, int32_t b)
+{
+    for (;;) {
+        a = uf_find<SCOPE>(L, a);
+        b = uf_find<SCOPE>(L, b);
+        if (a == b) return;
+        if (a > b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        const int32_t old = atomicMin(L + b, a);
+        if (old == b) return;
+        b = old;
+    }
+}
+
+// First and last column of the run of set bits of m that holds bit x.
+__device__ __forceinline__ int run_start(uint64_t m, int x)
+{
+    const uint64_t below = ~m & ((1ull << x) - 1); // clear bits under x
+    return below ? 64 - __clzll((long long)below) : 0;
+}
+
+__device__ __forceinline__ int run_end(uint64_t m, int x)
+{
+    const uint64_t above = x == 63 ? 0ull : ~m & ~((2ull << x) - 1); // clear bits over x
+    return above ? __ffsll((long long)above) - 2 : 63;
+}
+
+// Bit-parallel tile morphology. A tile row with its halo (64 + 8R columns
+// from ox0) is a 128-bit word, bit k = column ox0 + k; one lane holds one
+// row. An erosion (dilation) of radius R is the AND (OR) of the word shifted
+// by -R..R, then of the rows -R..R around it (neighbouring lanes). Cells
+// outside the frame are set to the operation's identity (1 for erosion, 0
+// for dilation) before each pass, which is what restricting the square to
+// the frame means. Shifts bring garbage only into the outer R columns and
+// rows of what was valid, which is exactly where the result stops being
+// valid (operation k leaves rows and columns [(k+1) R, S - (k+1) R)).
+typedef unsigned __int128 u128;
+
+__device__ __forceinline__ u128 shfl128(u128 v, int src)
+{
+    const uint64_t lo = __shfl((unsigned long long)(uint64_t)v, src, 64);
+    const uint64_t hi = __shfl((unsigned long long)(uint64_t)(v >> 64), src, 64);
+    return ((u128)hi << 64) | lo;
+}
+
+// bits [k0, k1] of a 128-bit word (empty when k1 < k0)
+__device__ __forceinline__ u128 bit_range(int k0, int k1)
+{
+    if (k1 < k0) return 0;
+    const u128 upto = k1 >= 127 ? ~(u128)0 : (((u128)1 << (k1 + 1)) - 1);
+    return upto & ~(((u128)1 << k0) - 1);
+}
+
+template <int R, bool ERODE>
+__device__ __forceinline__ u128 morph_pass(u128 x, u128 valid, int lane)
+{
+    x = ERODE ? (x | ~valid) : (x & valid);
+    u128 e = x;
+#pragma unroll
+    for (int q = 1; q <= R; ++q) e = ERODE ? (e & (x << q) & (x >> q)) : (e | (x << q) | (x >> q));
+    e = ERODE ? (e | ~valid) : (e & valid);
+    u128 f = e;
+#pragma unroll
+    for (int q = 1; q <= R; ++q) {
+        const u128 up = shfl128(e, max(lane - q, 0)), dn = shfl128(e, min(lane + q, 63));
+        f = ERODE ? (f & up & dn) : (f | up | dn);
+    }
+    return f;
+}
+
+// grid: (ceil(w/64), ceil(h/32)), 256 threads as 64 columns x 4 rows
+template <int R>
+__global__ __launch_bounds__(256) void k_open_close(MorphArgs a)
+{
+    constexpr int HAL = 4 * R, SW = MO_TW + 2 * HAL, SH = MO_TH + 2 * HAL;
+    static_assert(SH <= 64, "one lane per tile row");
+    __shared__ uint64_t rows[SH][2];
+    __shared__ int32_t lbl[MO_TH * MO_TW];
+    __shared__ uint64_t rowmask[MO_TH];
+    const int ox0 = blockIdx.x * MO_TW - HAL, oy0 = blockIdx.y * MO_TH - HAL;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const uint32_t tb = a.st->tau2_bits;
+    const float mS = group_max(a.maxs_S);
+    // threshold decisions, every load of the thread in flight before the
+    // first ballot: wave ty takes rows ty + 4k, lane tx columns tx and tx + 64
+    constexpr int LR = (SH + 3) / 4;
+    bool d0[LR], d1[LR];
+    auto decide = [&](int y, int x) -> bool {
+        if (y < 0 || y >= a.h || x < 0 || x >= a.w) return false;
+        const float S = a.sal[(size_t)y * a.sal_pitch + x];
+        return a.top ? (__float_as_uint(S) > tb) : (sal_norm(S, mS) > a.thresh);
+    };
+#pragma unroll
+    for (int k = 0; k < LR; ++k) {
+        const int ly = ty + 4 * k;
+        d0[k] = ly < SH && decide(oy0 + ly, ox0 + tx);
+        d1[k] = ly < SH && tx + 64 < SW && decide(oy0 + ly, ox0 + tx + 64);
+    }
+#pragma unroll
+    for (int k = 0; k < LR; ++k) {
+        const int ly = ty + 4 * k;
+        const uint64_t lo = __ballot(d0[k]), hi = __ballot(d1[k]);
+        if (ly < SH && tx == 0) {
+            rows[ly][0] = lo;
+            rows[ly][1] = hi;
+        }
+    }
+    __syncthreads();
+    const int ty0 = blockIdx.y * MO_TH, tx0 = blockIdx.x * MO_TW;
+    const int th = min(MO_TH, a.h - ty0), tw = min(MO_TW, a.w - tx0);
+    if (ty == 0) {
+        // wave 0, lane = tile row with halo: erode, dilate (opening), dilate,
+        // erode (closing)
+        const int ly = min(tx, SH - 1), y = oy0 + ly;
+        const u128 valid = y >= 0 && y < a.h ? bit_range(max(0, -ox0), min(SW - 1, a.w - 1 - ox0)) : 0;
+        u128 x = ((u128)rows[ly][1] << 64) | rows[ly][0];
+        if constexpr (R > 0) {
+            x = morph_pass<R, true>(x, valid, tx);
+            x = morph_pass<R, false>(x, valid, tx);
+            x = morph_pass<R, false>(x, valid, tx);
+            x = morph_pass<R, true>(x, valid, tx);
+        }
+        // the tile's own 64 columns, in-frame cells only
+        const uint64_t m = (uint64_t)((x & valid) >> HAL);
+        const int yt = tx - HAL;
+        if (yt >= 0 && yt < MO_TH) rowmask[yt] = yt < th ? m : 0;
+    }
+    __syncthreads();
+    if (!a.lab) {
+        for (int y = ty; y < th; y += 4)
+            if (tx < tw) a.pre[(size_t)(ty0 + y) * a.w + tx0 + tx] = (uint8_t)((rowmask[y] >> tx) & 1);
+        return;
+    }
+    // Local labelling over the tile's in-frame part, by horizontal runs: a
+    // wave holds one tile row, so the row's foreground is one ballot mask and
+    // each pixel finds its run's first column with a bit scan. Union-find
+    // nodes are runs (local index y 64 + first column); a run joins each run
+    // of the row above that overlaps it or touches it diagonally, once, at
+    // the leftmost column where that run begins to overlap (or at the run's
+    // ends for the diagonal contacts).
+    for (int y = ty; y < MO_TH; y += 4) {
+        const uint64_t m = rowmask[y];
+        lbl[y * MO_TW + tx] = (m >> tx) & 1 ? y * MO_TW + run_start(m, tx) : -1;
+    }
+    __syncthreads();
+    for (int y = ty; y < th; y += 4) {
+        const uint64_t m = rowmask[y];
+        if (y == 0 || !((m >> tx) & 1)) continue;
+        const uint64_t am = rowmask[y - 1];
+        const int s = run_start(m, tx), e = run_end(m, tx);
+        const int self = y * MO_TW + s, up = (y - 1) * MO_TW;
+        if (((am >> tx) & 1) && (tx == s || !((am >> (tx - 1)) & 1)))
+            uf_union<__HIP_MEMORY_SCOPE_WORKGROUP>(lbl, self, up + run_start(am, tx));
+        if (tx == s && s > 0 && ((am >> (s - 1)) & 1))
+            uf_union<__HIP_MEMORY_SCOPE_WORKGROUP>(lbl, self, up + run_start(am, s - 1));
+        if (tx == e && e < MO_TW - 1 && ((am >> (e + 1)) & 1))
+            uf_union<__HIP_MEMORY_SCOPE_WORKGROUP>(lbl, self, up + run_start(am, e + 1));
+    }
+    __syncthreads();
+    if (tx >= tw) return;
+    for (int y = ty; y < th; y += 4) {
+        const uint64_t m = rowmask[y];
+        const int32_t q = (ty0 + y) * a.w + tx0 + tx;
+        int32_t out = -1;
+        if ((m >> tx) & 1) {
+            const int root = uf_find<__HIP_MEMORY_SCOPE_WORKGROUP>(lbl, y * MO_TW + run_start(m, tx));
+            out = (ty0 + (root >> 6)) * a.w + tx0 + (root & 63);
+            if (root == y * MO_TW + tx) {
+                a.link[q] = q;
+                a.area[q] = 0;
+            }
+        }
+        a.lab[q] = out;
+    }
+}
+
+// Second pass: joins the tile roots of 8-adjacent foreground pixels that lie
+// in different tiles. Such a pair has its later pixel p on its tile's top
+// row (N, NW, NE cross), left column (W, NW cross) or right column (NE
+// crosses). One block per tile, thread t: t < 64 top row (0, t); t < 95
+// left column (t - 63, 0); t < 126 right column (t - 94, 63). A contact is
+// joined once, by the first pixel of a run of same-label pixels along the
+// border that touches it: p skips a neighbour that the previous pixel of
+// its border line (left on the top row, above on the left column) also
+// touches when that pixel carries the same label.
+// grid: (ceil(w/64), ceil(h/32)), 128 threads
+__global__ __launch_bounds__(128) void k_cc_border(const int32_t *lab, int32_t *link, int32_t h, int32_t w)
+{
+    const int t = threadIdx.x;
+    int ty, tx;
+    if (t < 64) {
+        ty = 0;
+        tx = t;
+    } else if (t < 95) {
+        ty = t - 63;
+        tx = 0;
+    } else if (t < 126) {
+        ty = t - 94;
+        tx = MO_TW - 1;
+    } else {
+        return;
+    }
+    const int y = blockIdx.y * MO_TH + ty, x = blockIdx.x * MO_TW + tx;
+    if (y >= h || x >= w) return;
+    const int32_t p = y * w + x;
+    const int32_t lp = lab[p];
+    if (lp < 0) return;
+    // the previous pixel along this border line, in the same tile
+    int32_t prev = -1;
+    if (ty == 0 && tx > 0) prev = lab[p - 1];
+    else if (tx == 0 && ty > 0) prev = lab[p - w];
+    const bool same_prev = prev == lp;
+    // labels of the cross-tile neighbours W, NW, N, NE (-1: none)
+    const int dy[4] = {0, -1, -1, -1}, dx[4] = {-1, -1, 0, 1};
+    int32_t lq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int qy = y + dy[k], qx = x + dx[k];
+        const bool cross = qy >= 0 && qx >= 0 && qx < w &&
+                           !(qy / MO_TH == (int)blockIdx.y && qx / MO_TW == (int)blockIdx.x);
+        lq[k] = cross ? lab[qy * w + qx] : -1;
+    }
+    if (same_prev) {
+        if (ty == 0 && tx > 0) {
+            // the left pixel touches NW and N of p (its N and NE), and joins
+            // the label of N, so NE is new only with another label
+            if (lq[3] == lq[2]) lq[3] = -1;
+            lq[1] = lq[2] = -1;
+        } else if (tx == 0 && ty > 0) {
+            // the pixel above touches NW of p (its W)
+            if (lq[0] == lq[1]) lq[0] = -1;
+            lq[1] = -1;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        bool seen = lq[k] < 0;
+#pragma unroll
+        for (int j = 0; j < k; ++j) seen |= lq[j] == lq[k];
+        if (!seen) uf_union<__HIP_MEMORY_SCOPE_AGENT>(link, lp, lq[k]);
+    }
+}
+
+// Third pass, one block per tile: counts the tile's pixels per tile root in
+// LDS (one atomic per segment of equal labels along a tile row: a wave holds
+// a row, a ballot marks where segments start), adds each count at the root
+// of the whole component, and relabels every pixel with that root.
+// grid: (ceil(w/64), ceil(h/32)), 256 threads as 64 columns x 4 rows
+__global__ __launch_bounds__(256) void k_cc_compress(int32_t *lab, int32_t *link, int32_t *area, int32_t h,
+                                                     int32_t w)
+{
+    __shared__ int32_t cnt[MO_TH * MO_TW];
+    __shared__ int32_t groot[MO_TH * MO_TW];
+    constexpr int PER = MO_TH / 4;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int ty0 = blockIdx.y * MO_TH, tx0 = blockIdx.x * MO_TW;
+    const int th = min(MO_TH, h - ty0), tw = min(MO_TW, w - tx0);
+    const int32_t base = ty0 * w + tx0;
+    const float inv_w = 1.0f / (float)w;
+    int32_t l[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int y = ty + 4 * k;
+        l[k] = y < th && tx < tw ? lab[base + y * w + tx] : -1;
+    }
+    for (int i = threadIdx.x; i < MO_TH * MO_TW; i += 256) cnt[i] = 0;
+    __syncthreads();
+    int16_t li[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        // the tile root lies in this tile: d = ry w + rx with ry < 32 and
+        // rx < min(64, w); the float quotient lands within one of ry and is
+        // corrected exactly
+        const int32_t d = l[k] >= 0 ? l[k] - base : 0;
+        const int32_t ry = (int32_t)((float)d * inv_w);
+        const int32_t ry2 = ry - (ry * w > d ? 1 : 0) + ((ry + 1) * w <= d ? 1 : 0);
+        li[k] = l[k] >= 0 ? (int16_t)(ry2 * MO_TW + (d - ry2 * w)) : (int16_t)-1;
+        const int32_t left = __shfl_up(l[k], 1, 64);
+        const bool head = l[k] >= 0 && (tx == 0 || left != l[k]);
+        const uint64_t H = __ballot(head), F = __ballot(l[k] >= 0);
+        if (head) {
+            // the segment runs to the next head or the next background pixel
+            const uint64_t after = tx == 63 ? 0ull : ~((2ull << tx) - 1);
+            const uint64_t stop = (H | ~F) & after;
+            const int end = stop ? __ffsll((long long)stop) - 1 : 64;
+            atomicAdd(&cnt[li[k]], end - tx);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < MO_TH * MO_TW; i += 256) {
+        const int c = cnt[i];
+        if (!c) continue;
+        const int32_t g = uf_find<__HIP_MEMORY_SCOPE_AGENT>(link, base + (i >> 6) * w + (i & 63));
+        groot[i] = g;
+        atomicAdd(area + g, c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+        if (li[k] >= 0) lab[base + (ty + 4 * k) * w + tx] = groot[li[k]];
 }
 
 // ---------------------------------------------------------------- adjacent-frame ensemble

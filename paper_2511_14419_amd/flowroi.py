@@ -21,9 +21,11 @@ ROI_U8, ROI_U16, ROI_F32 = 0, 1, 2
 ROI_THRESH_ABS, ROI_THRESH_TOP = 0, 1
 ROI_SE_SQUARE, ROI_SE_DISC = 0, 1
 ROI_USE_INITIAL_FLOW, ROI_FP16_STORAGE = 1, 2
+ROI_RULE_MAGNITUDE, ROI_RULE_SALIENCY = 0, 1
 
 EXPORTED = [
     "roi_default_params", "roi_validate", "roi_workspace_size", "roi_mask", "roi_read_tau2",
+    "roi_flow_mask_workspace_size", "roi_mask_from_flow",
     "roi_pyr_down", "roi_poly_expand", "roi_denoise", "roi_batched_workspace_size", "roi_mask_batched",
     "roi_stream_create", "roi_stream_push", "roi_stream_reset", "roi_stream_state_bytes",
     "roi_stream_destroy", "roi_stream_push_many", "roi_timing_enable", "roi_timing_read",
@@ -45,7 +47,9 @@ class RoiParams(ctypes.Structure):
                 ("thresh_mode", ctypes.c_int32), ("thresh", ctypes.c_float),
                 ("dilate_radius", ctypes.c_int32), ("se_shape", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("denoise", ctypes.c_int32), ("median_radius", ctypes.c_int32), ("bilateral_radius", ctypes.c_int32),
-                ("sigma_space", ctypes.c_float), ("sigma_range", ctypes.c_float), ("adjacent", ctypes.c_int32)]
+                ("sigma_space", ctypes.c_float), ("sigma_range", ctypes.c_float), ("adjacent", ctypes.c_int32),
+                ("rule", ctypes.c_int32), ("sal_weight", ctypes.c_float), ("morph_radius", ctypes.c_int32),
+                ("min_area", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -89,6 +93,10 @@ def lib():
         L.roi_mask.restype = i32
         L.roi_read_tau2.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_float), vp]
         L.roi_read_tau2.restype = i32
+        L.roi_flow_mask_workspace_size.argtypes = [i32, i32, pp]
+        L.roi_flow_mask_workspace_size.restype = sz
+        L.roi_mask_from_flow.argtypes = [vp, i32, i32, pp, vp, vp, vp, sz, vp]
+        L.roi_mask_from_flow.restype = i32
         L.roi_pyr_down.argtypes = [vp, i32, i32, vp, vp]
         L.roi_pyr_down.restype = i32
         L.roi_poly_expand.argtypes = [vp, i32, i32, i64, i32, pp, vp, vp]
@@ -239,6 +247,30 @@ def read_tau2(ws, index=0, stream=None):
     _check(lib().roi_read_tau2(ctypes.c_void_p(ws.data_ptr()), index, ctypes.byref(v), _stream(stream)),
            "roi_read_tau2")
     return v.value
+
+
+def mask_from_flow(flow, params=None, want_saliency=False, ws=None, stream=None):
+    """The mask stage alone on a device flow field (h, w, 2) float32.
+
+    Returns (mask (h, w) uint8, normalised saliency (h, w) float32 or None, ws)."""
+    params = params or default_params()
+    if flow.dtype != torch.float32 or flow.dim() != 3 or flow.shape[2] != 2 or not flow.is_contiguous():
+        raise ValueError("flow must be a contiguous (h, w, 2) float32 tensor")
+    h, w = flow.shape[:2]
+    dev = flow.device
+    mask = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    sal = torch.empty((h, w), dtype=torch.float32, device=dev) if want_saliency else None
+    need = lib().roi_flow_mask_workspace_size(h, w, ctypes.byref(params))
+    if need == 0:
+        raise RoiError(ROI_EINVAL, "roi_flow_mask_workspace_size")
+    if ws is None or ws.numel() < need:
+        ws = alloc_workspace(need, dev)
+    _check(lib().roi_mask_from_flow(ctypes.c_void_p(flow.data_ptr()), h, w, ctypes.byref(params),
+                                    ctypes.c_void_p(mask.data_ptr()),
+                                    ctypes.c_void_p(sal.data_ptr() if sal is not None else 0),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+           "roi_mask_from_flow")
+    return mask, sal, ws
 
 
 def pyr_down(src, stream=None):

@@ -23,6 +23,15 @@ between frames. The recipes:
   {1024^2, 1536^2, 2048^2, 2448(W) x 2048(H)}, round-robin, with
   200 * area / 2048^2 blobs per stream and seeds 200 + stream index.
 
+* ``flow_field(h, w, seed)``: a synthetic flow field for the mask stage
+  alone: a smooth background drift (two ``smooth_texture`` fields with sigma
+  8 px scaled to std 0.3 px) plus n_cells discs of radius ~ U[6, 20] px
+  moving with velocity drawn from the disc |v| <= 4 px, float32.
+* ``binary_pattern(h, w, kind, seed)``: uint8 0/1 patterns for the
+  morphology and component stages ("noise": i.i.d. with density 0.5;
+  "blobs": smoothed noise above its 70 % quantile; "snake": one 1-px wide
+  path winding over the whole frame; "full"; "empty"; "dot": one pixel).
+
 All randomness comes from numpy's PCG64 generator seeded explicitly.
 """
 from __future__ import annotations
@@ -36,6 +45,8 @@ __all__ = [
     "lens_stream_sizes",
     "lens_streams",
     "smooth_texture",
+    "flow_field",
+    "binary_pattern",
 ]
 
 # Blobs are rendered inside +-5 sigma; the Gaussian tail beyond is < 4e-6 of
@@ -139,3 +150,48 @@ def smooth_texture(h, w, seed, sigma=2.0, amplitude=100.0, pad=16):
         g += kv * np.roll(f, i, axis=1)
     g *= amplitude / g.std()
     return g
+
+
+def flow_field(h, w, seed, n_cells=None, max_speed=4.0):
+    """Synthetic (h, w, 2) float32 flow: smooth drift plus moving discs."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if n_cells is None:
+        n_cells = max(1, h * w // 8000)
+    f = np.zeros((h, w, 2))
+    for c in range(2):
+        f[..., c] = 0.1 * smooth_texture(h, w, seed * 7 + c, sigma=8.0, amplitude=3.0, pad=0)
+    yy, xx = np.mgrid[0:h, 0:w]
+    for _ in range(n_cells):
+        r = rng.uniform(6, 20)
+        cy, cx = rng.uniform(0, h), rng.uniform(0, w)
+        ang, mag = rng.uniform(0, 2 * np.pi), max_speed * np.sqrt(rng.uniform())
+        inside = (yy - cy) ** 2 + (xx - cx) ** 2 <= r * r
+        f[inside, 0] = mag * np.cos(ang)
+        f[inside, 1] = mag * np.sin(ang)
+    return f.astype(np.float32)
+
+
+def binary_pattern(h, w, kind, seed=0):
+    """uint8 0/1 test patterns (see the module docstring)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if kind == "noise":
+        return (rng.uniform(size=(h, w)) < 0.5).astype(np.uint8)
+    if kind == "blobs":
+        t = smooth_texture(h, w, seed, sigma=3.0, pad=0)
+        return (t > np.quantile(t, 0.7)).astype(np.uint8)
+    if kind == "snake":
+        m = np.zeros((h, w), np.uint8)
+        for y in range(0, h, 4):
+            m[y, :] = 1
+            x = w - 1 if (y // 4) % 2 == 0 else 0
+            m[y:y + 4, x] = 1
+        return m
+    if kind == "full":
+        return np.ones((h, w), np.uint8)
+    if kind == "empty":
+        return np.zeros((h, w), np.uint8)
+    if kind == "dot":
+        m = np.zeros((h, w), np.uint8)
+        m[h // 2, w // 2] = 1
+        return m
+    raise ValueError(kind)

@@ -41,6 +41,8 @@ def test_defaults(F):
     assert (p.thresh_mode, p.thresh, p.dilate_radius, p.se_shape, p.flags) == (0, 1.0, 2, 0, 0)
     assert (p.denoise, p.median_radius, p.bilateral_radius) == (0, 1, 2)
     assert abs(p.sigma_space - 1.5) < 1e-6 and abs(p.sigma_range - 20.0) < 1e-6
+    assert (p.adjacent, p.rule, p.morph_radius, p.min_area) == (0, F.ROI_RULE_MAGNITUDE, 1, 32)
+    assert abs(p.sal_weight - 0.7) < 1e-6
 
 
 @pytest.mark.parametrize("kw,h,w,dtype,expect", [
@@ -78,6 +80,15 @@ def test_defaults(F):
     ({"adjacent": 2}, 64, 64, 0, 0),
     ({"adjacent": -1}, 64, 64, 0, -1),
     ({"adjacent": 9}, 64, 64, 0, -4),
+    ({"rule": 1}, 64, 64, 0, 0),
+    ({"rule": 2}, 64, 64, 0, -1),
+    ({"rule": 1, "thresh_mode": 1, "thresh": 0.2}, 64, 64, 0, 0),
+    ({"rule": 1, "sal_weight": 1.5}, 64, 64, 0, -1),
+    ({"rule": 1, "sal_weight": float("nan")}, 64, 64, 0, -1),
+    ({"rule": 1, "morph_radius": -1}, 64, 64, 0, -1),
+    ({"rule": 1, "morph_radius": 3}, 64, 64, 0, -4),
+    ({"rule": 1, "min_area": -2}, 64, 64, 0, -1),
+    ({"rule": 0, "morph_radius": 7, "min_area": -2}, 64, 64, 0, 0),
 ])
 def test_validate(F, kw, h, w, dtype, expect):
     assert F.validate(h, w, dtype, F.default_params(**kw)) == expect
@@ -113,6 +124,24 @@ def test_roi_mask_rejects_before_launch(F):
     assert L.roi_mask(fake, fake, 64, 64, 64, 0, ctypes.byref(bad), fake, fake, ws, 1 << 30, None) == F.ROI_EINVAL
     # empty frame: no-op
     assert L.roi_mask(None, None, 0, 64, 64, 0, ctypes.byref(p), None, None, None, 0, None) == F.ROI_OK
+
+
+def test_mask_from_flow_rejects_before_launch(F):
+    L = F.lib()
+    p = F.default_params(rule=F.ROI_RULE_SALIENCY)
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x100000)
+    need = L.roi_flow_mask_workspace_size(64, 64, ctypes.byref(p))
+    assert need > L.roi_flow_mask_workspace_size(0, 64, ctypes.byref(p)) > 0
+    assert L.roi_flow_mask_workspace_size(64, 64, ctypes.byref(F.default_params(rule=5))) == 0
+    assert L.roi_mask_from_flow(None, 64, 64, ctypes.byref(p), fake, None, ws, need, None) == F.ROI_EINVAL
+    assert L.roi_mask_from_flow(fake, 64, 64, ctypes.byref(p), None, None, ws, need, None) == F.ROI_EINVAL
+    assert L.roi_mask_from_flow(fake, 64, 64, ctypes.byref(p), fake, None, ctypes.c_void_p(0x100040), need,
+                                None) == F.ROI_EINVAL
+    assert L.roi_mask_from_flow(fake, 64, 64, ctypes.byref(p), fake, None, ws, need - 1, None) == F.ROI_ENOMEM
+    bad = F.default_params(rule=1, morph_radius=3)
+    assert L.roi_mask_from_flow(fake, 64, 64, ctypes.byref(bad), fake, None, ws, 1 << 30, None) == F.ROI_EUNSUPPORTED
+    assert L.roi_mask_from_flow(None, 0, 64, ctypes.byref(p), None, None, None, 0, None) == F.ROI_OK
 
 
 def test_batched_and_stream_reject_before_launch(F):

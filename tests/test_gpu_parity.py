@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import DELTA, check_mask, device, to_dev
+from gpu_util import DELTA, check_mask, check_sandwich, device, saliency_delta, to_dev
 from paper_2511_14419_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -279,6 +279,16 @@ def test_full_size_2048_u16_pair():
     assert err.max() <= DELTA
     checked, band = check_mask(mask, ref_flow, ref_t2, 2, 0, DELTA)
     say("  mask: %d pixels checked, %d band pixels" % (checked, band))
+    # the paper's saliency rule on the same pair (top 20 % of saliency)
+    fl = F()
+    p = fl.default_params(rule=fl.ROI_RULE_SALIENCY, thresh_mode=1, thresh=0.2)
+    f2, m2, _ = fl.roi_mask(to_dev(seq[0], dev), to_dev(seq[1], dev), p)
+    torch.cuda.synchronize()
+    assert np.array_equal(f2.cpu().numpy(), flow.astype(np.float32))
+    s_ref = oracle.saliency(ref_flow, float(np.float32(0.7)))
+    d = saliency_delta(ref_flow, err.max(), 0.7)
+    gap = check_sandwich(m2.cpu().numpy(), s_ref, p, 2 * d)
+    say("  saliency rule: delta %.3g, sandwich gap %d px" % (d, gap))
 
 
 def _pairs(dev, sizes, seed0=40):
