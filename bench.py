@@ -165,6 +165,13 @@ def main():
     if not args.no_extras:
         out["plain_denoise"] = bench_plain_variant(fl, frames, flows, masks, dev, args,
                                                    fl.default_params(denoise=1, sigma_range=60.0), "denoise on")
+        out["plain_saliency_rule"] = bench_plain_variant(
+            fl, frames, flows, masks, dev, args, fl.default_params(rule=fl.ROI_RULE_SALIENCY, thresh_mode=1, thresh=0.2),
+            "saliency rule: top 20 % of saliency (weight 0.7), 3x3 opening+closing, components >= 32 px")
+        out["plain_top_fraction"] = bench_plain_variant(fl, frames, flows, masks, dev, args,
+                                                        fl.default_params(thresh_mode=1, thresh=0.2),
+                                                        "magnitude rule, top 20 % of |d|")
+        out["mask_stage_us"] = bench_mask_stage(fl, flows[0], args)
         out["streaming"] = bench_streaming(fl, frames, p, dev, args)
         out["streaming_adjacent2"] = bench_streaming(fl, frames, fl.default_params(adjacent=2), dev, args)
         out["batched"] = bench_batched(fl, dev, args, fp16=False)
@@ -196,6 +203,32 @@ def bench_plain_variant(fl, frames, flows, masks, dev, args, p, name):
     r = {"frames_per_s": round(npairs * reps / (time.perf_counter() - t0), 2), "params": name}
     log("plain (%s): %.1f frames/s" % (name, r["frames_per_s"]))
     return r
+
+
+def bench_mask_stage(fl, flow, args):
+    """GPU time of the mask stage alone (roi_mask_from_flow) on one 2048x2048
+    flow field, per rule, microseconds per call."""
+    import torch
+    rules = {
+        "magnitude_abs_1px": fl.default_params(),
+        "magnitude_top20": fl.default_params(thresh_mode=1, thresh=0.2),
+        "saliency_top20_cc32": fl.default_params(rule=fl.ROI_RULE_SALIENCY, thresh_mode=1, thresh=0.2),
+        "saliency_top20_no_cc": fl.default_params(rule=fl.ROI_RULE_SALIENCY, thresh_mode=1, thresh=0.2, min_area=0),
+    }
+    out = {}
+    for name, p in rules.items():
+        m, _, ws = fl.mask_from_flow(flow, p)
+        torch.cuda.synchronize()
+        n = 20 * max(1, args.steps // 5)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fl.mask_from_flow(flow, p, ws=ws, mask=m)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(1e3 * e0.elapsed_time(e1) / n, 2)
+    log("mask stage alone (us): %s" % out)
+    return out
 
 
 def bench_streaming(fl, frames, p, dev, args):

@@ -264,14 +264,89 @@ def saliency_mask(flow, thresh_mode=1, thresh=0.2, weight=0.7, morph_radius=1, m
     return dilate(m, dilate_radius, se_shape), s, tau
 
 
+# ---------------------------------------------------------------- stabilisation
+
+PHASE_MAX = 2048
+
+
+def phase_size(h, w):
+    """Side P of the square window the translation is estimated on: the
+    largest power of two <= min(h, w, 2048); 0 when the frame is thinner
+    than 2 pixels."""
+    m = min(h, w, PHASE_MAX)
+    if m < 2:
+        return 0
+    return 1 << (int(m).bit_length() - 1)
+
+
+def hann(n):
+    """Symmetric Hann window of n points: 0.5 (1 - cos(2 pi i / (n - 1)))."""
+    i = np.arange(n, dtype=np.float64)
+    return 0.5 * (1.0 - np.cos(2.0 * np.pi * i / (n - 1)))
+
+
+def phase_correlation(prev, next):
+    """Phase-correlation surface of two frames (FlowRoI, Method, optical
+    flow extraction: frames are registered to their predecessor by phase
+    correlation). Both frames are cut to the centred P x P window and
+    multiplied by the separable Hann window; with A, B their 2-D DFTs,
+    r = IDFT(B conj(A) / |B conj(A)|) (0 where the product is 0). If next
+    is prev moved by s (next(x) = prev(x - s)), then B = A e^{-2 pi i k s / P},
+    the normalised product is that phase ramp alone and r peaks at s
+    modulo P.
+    Returns (r, P, y0, x0) with (y0, x0) the window's corner."""
+    a, b = _f64(prev), _f64(next)
+    h, w = a.shape
+    P = phase_size(h, w)
+    y0, x0 = (h - P) // 2, (w - P) // 2
+    win = np.outer(hann(P), hann(P))
+    A = np.fft.fft2(a[y0:y0 + P, x0:x0 + P] * win)
+    B = np.fft.fft2(b[y0:y0 + P, x0:x0 + P] * win)
+    X = B * np.conj(A)
+    mag = np.abs(X)
+    R = np.where(mag > 0, X / np.where(mag > 0, mag, 1.0), 0.0)
+    return np.fft.ifft2(R).real, P, y0, x0
+
+
+def phase_shift(prev, next):
+    """Integer translation (sy, sx) of next relative to prev: the position of
+    the largest value of the phase-correlation surface (the first in row-major
+    order on ties), indices at or above P/2 read as negative. Returns
+    (sy, sx, peak value); (0, 0, 0.0) for frames thinner than 2 pixels."""
+    h, w = np.shape(prev)
+    if phase_size(h, w) == 0:
+        return 0, 0, 0.0
+    r, P, _, _ = phase_correlation(prev, next)
+    k = int(np.argmax(r))
+    py, px = divmod(k, P)
+    sy = py - P if py >= P // 2 else py
+    sx = px - P if px >= P // 2 else px
+    return sy, sx, float(r.flat[k])
+
+
+def align(next, sy, sx):
+    """next moved back by (sy, sx): out(y, x) = next(y + sy, x + sx), the
+    coordinates clamped into the frame (replicated edges)."""
+    q = _f64(next)
+    h, w = q.shape
+    ys = np.clip(np.arange(h) + sy, 0, h - 1)
+    xs = np.clip(np.arange(w) + sx, 0, w - 1)
+    return q[np.ix_(ys, xs)]
+
+
 def roi_mask(prev, next, levels=3, winsize=15, iterations=3, poly_n=5, poly_sigma=1.1, eps=1e-3,
-             thresh_mode=0, thresh=1.0, dilate_radius=2, se_shape=0, init=None, denoise_params=None):
+             thresh_mode=0, thresh=1.0, dilate_radius=2, se_shape=0, init=None, denoise_params=None,
+             stabilize=False):
     """Whole path: returns (flow (h, w, 2), mask (h, w) uint8 0/1, tau^2).
     denoise_params (dict of denoise()'s keywords) applies the denoising
-    pre-stage to both frames first."""
+    pre-stage to both frames first; stabilize then registers next to prev
+    (phase_shift, align) before the flow, in the paper's order."""
     p, q = _f64(prev), _f64(next)
     if denoise_params is not None:
         p, q = denoise(p, **denoise_params), denoise(q, **denoise_params)
+    if stabilize:
+        sy, sx, _ = phase_shift(p, q)
+        q = align(q, sy, sx)
     h, w = p.shape
     fl = np.empty((h, w, 2))
     mask = np.empty((h, w), dtype=np.uint8)

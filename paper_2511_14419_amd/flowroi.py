@@ -249,7 +249,7 @@ def read_tau2(ws, index=0, stream=None):
     return v.value
 
 
-def mask_from_flow(flow, params=None, want_saliency=False, ws=None, stream=None):
+def mask_from_flow(flow, params=None, want_saliency=False, ws=None, stream=None, mask=None):
     """The mask stage alone on a device flow field (h, w, 2) float32.
 
     Returns (mask (h, w) uint8, normalised saliency (h, w) float32 or None, ws)."""
@@ -258,7 +258,10 @@ def mask_from_flow(flow, params=None, want_saliency=False, ws=None, stream=None)
         raise ValueError("flow must be a contiguous (h, w, 2) float32 tensor")
     h, w = flow.shape[:2]
     dev = flow.device
-    mask = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    if mask is None:
+        mask = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    elif mask.shape != (h, w) or mask.dtype != torch.uint8 or not mask.is_contiguous():
+        raise ValueError("mask must be a contiguous (h, w) uint8 tensor")
     sal = torch.empty((h, w), dtype=torch.float32, device=dev) if want_saliency else None
     need = lib().roi_flow_mask_workspace_size(h, w, ctypes.byref(params))
     if need == 0:

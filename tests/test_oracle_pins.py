@@ -400,3 +400,86 @@ def test_saliency_mask_top_fraction():
     mask, s, tau = oracle.saliency_mask(fl, 1, 0.2)
     assert (s > tau).sum() <= int(np.floor(0.2 * s.size))
     assert mask.any() and mask.mean() < 0.6
+
+
+# --------------------------------------------------------------------------- stabilisation (phase correlation)
+
+def _dft2(x):
+    """Textbook 2-D DFT by explicit sums: X(k, l) = sum x(m, n) e^{-2 pi i (km/M + ln/N)}."""
+    M, N = x.shape
+    m = np.arange(M)
+    n = np.arange(N)
+    Fm = np.exp(-2j * np.pi * np.outer(m, m) / M)
+    Fn = np.exp(-2j * np.pi * np.outer(n, n) / N)
+    out = np.zeros((M, N), complex)
+    for k in range(M):
+        for l in range(N):
+            out[k, l] = np.sum(x * np.outer(Fm[k], Fn[l]))
+    return out
+
+
+def test_phase_correlation_matches_textbook_definition():
+    rng = np.random.default_rng(41)
+    a, b = rng.uniform(0, 255, (11, 13)), rng.uniform(0, 255, (11, 13))
+    r, P, y0, x0 = oracle.phase_correlation(a, b)
+    assert (P, y0, x0) == (8, 1, 2)
+    win = np.outer(0.5 - 0.5 * np.cos(2 * np.pi * np.arange(8) / 7), 0.5 - 0.5 * np.cos(2 * np.pi * np.arange(8) / 7))
+    A = _dft2(a[1:9, 2:10] * win)
+    B = _dft2(b[1:9, 2:10] * win)
+    X = B * np.conj(A)
+    R = X / np.abs(X)
+    # inverse DFT by the same explicit sums: x(m, n) = (1/MN) sum X(k, l) e^{+2 pi i (...)}
+    ref = np.conj(_dft2(np.conj(R))).real / 64
+    np.testing.assert_allclose(r, ref, atol=1e-12)
+
+
+def test_phase_shift_circular_closed_form():
+    """For a circular shift inside the window the normalised cross power is a
+    pure phase ramp when no window is applied; with the Hann window the peak
+    still lands exactly on the shift for a broadband texture."""
+    tex = synth.smooth_texture(256, 256, 3, sigma=1.0, pad=0)
+    for s in [(0, 0), (3, -5), (-7, 2), (12, 0), (0, -13)]:
+        moved = np.roll(tex, s, axis=(0, 1))
+        sy, sx, peak = oracle.phase_shift(tex, moved)
+        assert (sy, sx) == s and peak > 0.3
+
+
+def test_phase_shift_sign_and_align_on_translated_frames():
+    """next = prev moved by s (next(x) = prev(x - s)): the estimate is s and
+    aligning next by it gives back prev away from the entering border."""
+    big = synth.smooth_texture(300, 340, 7, sigma=1.5, pad=40)
+    for s in [(4, -6), (-9, 3), (0, 0), (1, 1)]:
+        prev = big[40:340, 40:380]
+        nxt = big[40 - s[0]:340 - s[0], 40 - s[1]:380 - s[1]]
+        sy, sx, _ = oracle.phase_shift(prev, nxt)
+        assert (sy, sx) == s
+        al = oracle.align(nxt, sy, sx)
+        m = 16
+        np.testing.assert_array_equal(al[m:-m, m:-m], prev[m:-m, m:-m])
+
+
+def test_phase_size_and_align_edges():
+    assert oracle.phase_size(2048, 2448) == 2048
+    assert oracle.phase_size(1536, 1536) == 1024
+    assert oracle.phase_size(5, 300) == 4
+    assert oracle.phase_size(1, 300) == 0
+    assert oracle.phase_shift(np.ones((1, 7)), np.ones((1, 7))) == (0, 0, 0.0)
+    x = np.arange(12.0).reshape(3, 4)
+    np.testing.assert_array_equal(oracle.align(x, 1, -2), x[np.ix_([1, 2, 2], [0, 0, 0, 1])])
+    # identical frames: zero shift, peak 1 (the surface is a unit delta)
+    f = synth.smooth_texture(64, 64, 2, pad=0)
+    sy, sx, peak = oracle.phase_shift(f, f)
+    assert (sy, sx) == (0, 0) and abs(peak - 1.0) < 1e-12
+
+
+def test_stabilized_path_recovers_translated_pair():
+    """A globally translated pair: with stabilisation the flow is the residual
+    (near zero), without it the flow carries the translation."""
+    big = synth.smooth_texture(96, 128, 9, sigma=2.0, pad=16)
+    prev = big[16:112, 16:144]
+    nxt = big[16 - 2:112 - 2, 16 + 3:144 + 3]  # next(x) = prev(x - (2, -3))
+    f0, _, _ = oracle.roi_mask(prev, nxt)
+    f1, _, _ = oracle.roi_mask(prev, nxt, stabilize=True)
+    c = (slice(24, -24), slice(24, -24))
+    assert abs(np.median(f0[c][..., 0]) + 3) < 0.2 and abs(np.median(f0[c][..., 1]) - 2) < 0.2
+    assert np.abs(f1[c]).max() < 0.05
