@@ -78,8 +78,10 @@ enum {
 
 enum {
     ROI_USE_INITIAL_FLOW = 1u, /* `flow` holds an initial flow on entry (see roi_mask) */
-    ROI_FP16_STORAGE = 2u      /* per-level expansions (the planes every iteration reads) stored as FP16;
+    ROI_FP16_STORAGE = 2u,     /* per-level expansions (the planes every iteration reads) stored as FP16;
                                   pyramid images stay FP64, all arithmetic FP32/FP64 as without it */
+    ROI_STABILIZE = 4u         /* register next to prev before the flow (Method, optical flow extraction:
+                                  phase-correlation alignment, after denoising); see roi_phase_correlation */
 };
 
 /* Parameters of the path. Farneback's constants are not given by the paper
@@ -155,6 +157,42 @@ roi_status roi_mask(const void *prev, const void *next, int32_t h, int32_t w, in
  * with TOP it is the (k+1)-th largest saliency before normalisation (S,
  * not squared); under the saliency rule with ABS it is 0. */
 roi_status roi_read_tau2(const void *ws, int32_t index, float *tau2_out, void *stream);
+
+/* Translation (sy, sx) that stabilisation applied in the last roi_mask,
+ * roi_mask_batched (pair `index`) or roi_phase_correlation call on this
+ * workspace, and the correlation peak (peak may be NULL); copied to the
+ * host after synchronising `stream`. Meaningful only after a call that ran
+ * stabilisation. */
+roi_status roi_read_shift(const void *ws, int32_t index, int32_t *sy, int32_t *sx, float *peak, void *stream);
+
+/* ---- Stabilisation (Method, optical flow extraction) --------------------
+ * Registration of a frame to its predecessor by phase correlation. Both
+ * frames are cut to the centred P x P window, P = roi_phase_size(h, w)
+ * (the largest power of two <= min(h, w, 2048); 0 for frames thinner than
+ * 2 pixels: no estimate, zero shift), multiplied by the separable Hann
+ * window 0.5 (1 - cos(2 pi i / (P - 1))); with A, B their 2-D DFTs the
+ * surface r = IDFT(B conj(A) / |B conj(A)|) (0 where the product is 0)
+ * peaks at the translation s of next against prev (next(x) = prev(x - s)):
+ * its largest value (first in row-major order on ties), indices at or above
+ * P/2 read as negative. The registered frame is next moved back by s,
+ * out(y, x) = next(y + sy, x + sx), coordinates clamped into the frame.
+ * Under ROI_STABILIZE, roi_mask computes the flow from prev to the
+ * registered next (after the denoising pre-stage when it is on); a stream
+ * registers each frame to its registered predecessor (the first is kept). */
+int32_t roi_phase_size(int32_t h, int32_t w);
+size_t roi_phase_workspace_size(int32_t h, int32_t w);
+
+/* The stabilisation step alone.
+ *   prev, next  device h x w frames of `dtype`, row pitch `pitch` elements.
+ *   surface     device P*P floats (row-major, P = roi_phase_size), output of
+ *               the correlation surface; may be NULL.
+ *   aligned     device h*w floats (pitch w), output of the registered next
+ *               frame; may be NULL.
+ *   ws          device workspace >= roi_phase_workspace_size(h, w) bytes,
+ *               256-byte aligned; roi_read_shift(ws, 0, ...) reads the shift. */
+roi_status roi_phase_correlation(const void *prev, const void *next, int32_t h, int32_t w, int64_t pitch,
+                                 roi_dtype dtype, float *surface, float *aligned, void *ws, size_t ws_bytes,
+                                 void *stream);
 
 /* Workspace bytes roi_mask_from_flow needs (0 if the parameters fail the
  * checks of roi_validate that concern the mask stage). */
@@ -241,6 +279,10 @@ roi_status roi_stream_reset(void *ctx);
 size_t roi_stream_state_bytes(int32_t h, int32_t w, roi_dtype dtype, const roi_params *p);
 
 void roi_stream_destroy(void *ctx);
+
+/* The translation stabilisation applied to the last frame pushed to this
+ * stream (0, 0 for its first frame), as roi_read_shift. */
+roi_status roi_stream_read_shift(void *ctx, int32_t *sy, int32_t *sx, float *peak, void *stream);
 
 /* Several stream contexts advanced together: frames[i] is pushed into
  * ctxs[i], all in one batched launch sequence on `stream`. status[i] gets

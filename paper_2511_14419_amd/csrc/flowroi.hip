@@ -31,7 +31,25 @@ namespace {
 constexpr size_t ALIGN = 256;
 constexpr int MAX_LEVELS = 10;
 constexpr int MAX_BATCH = 256;
-constexpr size_t HDR_BYTES = sizeof(SelState) * MAX_BATCH; // per-pair threshold state slots
+// per-pair state slots at the start of every workspace: the threshold state
+// of each pair, then the translation found by stabilisation
+constexpr size_t HDR_BYTES = (sizeof(SelState) + sizeof(PhaseState)) * MAX_BATCH;
+
+PhaseState *phase_slot(void *ws, int index)
+{
+    return (PhaseState *)((uint8_t *)ws + sizeof(SelState) * MAX_BATCH) + index;
+}
+
+// side of the square window the translation is estimated on: the largest
+// power of two <= min(h, w, PH_MAXP), 0 when the frame is thinner than 2
+int phase_size(int h, int w)
+{
+    const int m = std::min(std::min(h, w), PH_MAXP);
+    if (m < 2) return 0;
+    int P = 1;
+    while (P * 2 <= m) P *= 2;
+    return P;
+}
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -60,7 +78,10 @@ struct Plan {
     size_t ts;        // storage bytes per expansion value
     size_t is;        // storage bytes per pyramid image value (FP64)
     Level lv[MAX_LEVELS];
-    size_t den[2];    // denoised level-0 frames (floats, pitch lv[0].pitch), when denoising
+    size_t den[2];    // level-0 frames as floats (pitch lv[0].pitch): denoised, or converted for stabilisation
+    size_t al[2];     // registered level-0 frames (floats, pitch lv[0].pitch), when stabilising
+    int ph_P;         // stabilisation window side (0: none)
+    size_t ph_z, ph_t, ph_tw, ph_hann, ph_keys;
     size_t init_off;  // coarsest-level initial flow
     size_t m2_off;    // |d|^2 at full resolution, pitch lv[0].pitch
     size_t hist_off;  // radix-select histogram
@@ -99,8 +120,21 @@ Plan make_plan(int h, int w, const roi_params *p)
         v.fa = take(plane * sizeof(float2));
         v.fb = l > 0 ? take(plane * sizeof(float2)) : 0;
     }
-    for (int f = 0; f < 2; ++f)
-        pl.den[f] = p->denoise ? take((size_t)pl.lv[0].h * pl.lv[0].pitch * sizeof(float)) : 0;
+    const bool stab = (p->flags & ROI_STABILIZE) != 0;
+    const size_t fplane = (size_t)pl.lv[0].h * pl.lv[0].pitch * sizeof(float);
+    for (int f = 0; f < 2; ++f) {
+        pl.den[f] = p->denoise || stab ? take(fplane) : 0;
+        pl.al[f] = stab ? take(fplane) : 0;
+    }
+    pl.ph_P = stab ? phase_size(h, w) : 0;
+    if (pl.ph_P > 0) {
+        const size_t P = (size_t)pl.ph_P;
+        pl.ph_z = take(P * P * sizeof(float2));
+        pl.ph_t = take(P * P * sizeof(float2));
+        pl.ph_tw = take(P / 2 * sizeof(float2) + sizeof(float2));
+        pl.ph_hann = take(P * sizeof(float));
+        pl.ph_keys = take(PH_SLOTS * PH_SLOT_STRIDE * sizeof(unsigned long long));
+    }
     const Level &c = pl.lv[pl.L - 1];
     pl.init_off = take((size_t)c.h * c.pitch * sizeof(float2));
     pl.m2_off = take((size_t)pl.lv[0].h * pl.lv[0].pitch * sizeof(float));
@@ -278,8 +312,92 @@ roi_status launch_denoise(roi_dtype dt, const DenoiseArgs &a, const roi_params *
 }
 
 // Pyramid and expansions of `nf` (1 or 2) frames into expansion sets `set[]`.
+// Buffers of one phase correlation: P (0: no estimate, zero shift), the
+// two P x P complex fields, the tables and the argmax counters.
+struct PhaseBufs {
+    int P;
+    float2 *z, *t, *tw;
+    float *hann;
+    unsigned long long *keys;
+};
+
+template <typename TIn>
+void launch_to_float(const void *src, int64_t spitch, float *dst, int dpitch, int h, int w, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_float<TIn>, dim3((w + 63) / 64, (h + 3) / 4), dim3(256), 0, s, (const TIn *)src, spitch,
+                       dst, dpitch, h, w);
+}
+
+void to_float(roi_dtype dt, const void *src, int64_t spitch, float *dst, int dpitch, int h, int w, hipStream_t s)
+{
+    if (dt == ROI_U8) launch_to_float<uint8_t>(src, spitch, dst, dpitch, h, w, s);
+    else if (dt == ROI_U16) launch_to_float<uint16_t>(src, spitch, dst, dpitch, h, w, s);
+    else launch_to_float<float>(src, spitch, dst, dpitch, h, w, s);
+}
+
+// Registration of `mov` to `ref` (both h x w floats, row pitch `pitch`):
+// the translation by phase correlation over the centred P x P window, then
+// out(y, x) = mov(y + sy, x + sx) with clamped coordinates (row pitch
+// `opitch`); the shift goes to *ph. `surface` (nullable, P x P floats)
+// receives the correlation surface.
+roi_status enqueue_phase(const PhaseBufs &b, const float *ref, const float *mov, int pitch, int h, int w, float *out,
+                         int opitch, PhaseState *ph, float *surface, hipStream_t s)
+{
+    const int P = b.P;
+    if (P > 0) {
+        hipLaunchKernelGGL(k_ph_tables, dim3((P / 2 + P + 255) / 256), dim3(256), 0, s, b.tw, b.hann, b.keys, P);
+        PhArgs g{};
+        g.a = ref;
+        g.b = mov;
+        g.pitch = pitch;
+        g.y0 = (h - P) / 2;
+        g.x0 = (w - P) / 2;
+        g.P = P;
+        g.hann = b.hann;
+        g.z = b.z;
+        const dim3 ge((P + 63) / 64, (P + 3) / 4), gt((P + 31) / 32, (P + 31) / 32);
+        const size_t lds = 2 * (size_t)P * sizeof(float2);
+        hipLaunchKernelGGL(k_ph_pack, ge, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_fft_rows<false, false>), dim3(P), dim3(256), lds, s, b.z, P, (const float2 *)b.tw,
+                           (float *)nullptr, (unsigned long long *)nullptr);
+        hipLaunchKernelGGL(k_transpose, gt, dim3(256), 0, s, (const float2 *)b.z, b.t, P);
+        hipLaunchKernelGGL((k_fft_rows<false, false>), dim3(P), dim3(256), lds, s, b.t, P, (const float2 *)b.tw,
+                           (float *)nullptr, (unsigned long long *)nullptr);
+        hipLaunchKernelGGL(k_ph_cross, ge, dim3(256), 0, s, (const float2 *)b.t, b.z, P);
+        hipLaunchKernelGGL((k_fft_rows<true, false>), dim3(P), dim3(256), lds, s, b.z, P, (const float2 *)b.tw,
+                           (float *)nullptr, (unsigned long long *)nullptr);
+        hipLaunchKernelGGL(k_transpose, gt, dim3(256), 0, s, (const float2 *)b.z, b.t, P);
+        hipLaunchKernelGGL((k_fft_rows<true, true>), dim3(P), dim3(256), lds, s, b.t, P, (const float2 *)b.tw, surface,
+                           b.keys);
+    }
+    hipLaunchKernelGGL(k_ph_apply, dim3((w + 63) / 64, (h + 3) / 4), dim3(256), 0, s, mov, out, pitch, opitch, h, w,
+                       (const unsigned long long *)b.keys, P, ph);
+    LAUNCH_CHECK();
+    return ROI_OK;
+}
+
+PhaseBufs phase_bufs(const Plan &pl, uint8_t *base)
+{
+    PhaseBufs b{};
+    b.P = pl.ph_P;
+    if (b.P > 0) {
+        b.z = (float2 *)(base + pl.ph_z);
+        b.t = (float2 *)(base + pl.ph_t);
+        b.tw = (float2 *)(base + pl.ph_tw);
+        b.hann = (float *)(base + pl.ph_hann);
+        b.keys = (unsigned long long *)(base + pl.ph_keys);
+    }
+    return b;
+}
+
+// Level-0 inputs of nf frames (denoised and/or registered as the flags say),
+// then the pyramid and the expansions of every level into the sets set[f].
+// Stabilisation registers the last frame: to the first one (nf == 2), or to
+// the registered frame held in al[reg_set] (a stream; reg_set < 0 on its
+// first frame, which is kept as it is). ph receives the translation.
 roi_status enqueue_expand(const Plan &pl, uint8_t *base, int nf, const void *const *frames, int64_t pitch,
-                          roi_dtype dt, const roi_params *p, const int *set, hipStream_t s)
+                          roi_dtype dt, const roi_params *p, const int *set, hipStream_t s, PhaseState *ph = nullptr,
+                          int reg_set = -1)
 {
     const PolyConsts pc = poly_consts(p->poly_n, p->poly_sigma);
     const void *lvl0[2] = {frames[0], nf > 1 ? frames[1] : nullptr};
@@ -301,6 +419,26 @@ roi_status enqueue_expand(const Plan &pl, uint8_t *base, int nf, const void *con
         if (st != ROI_OK) return st;
         dt0 = ROI_F32; // denoised frames: floats in the input's grey levels
         pitch0 = pl.lv[0].pitch;
+    }
+    if (p->flags & ROI_STABILIZE) {
+        const int h = pl.lv[0].h, w = pl.lv[0].w, fp = pl.lv[0].pitch;
+        if (!p->denoise) {
+            for (int f = 0; f < nf; ++f) {
+                to_float(dt, frames[f], pitch, (float *)(base + pl.den[set[f]]), fp, h, w, s);
+                lvl0[f] = base + pl.den[set[f]];
+            }
+            dt0 = ROI_F32;
+            pitch0 = fp;
+        }
+        const int fn = set[nf - 1];
+        const float *ref = nf == 2 ? (const float *)(base + pl.den[set[0]])
+                                   : (reg_set >= 0 ? (const float *)(base + pl.al[reg_set]) : nullptr);
+        PhaseBufs b = phase_bufs(pl, base);
+        if (!ref) b.P = 0; // first frame of a stream: kept as it is
+        float *out = (float *)(base + pl.al[fn]);
+        roi_status st = enqueue_phase(b, ref, (const float *)(base + pl.den[fn]), fp, h, w, out, fp, ph, nullptr, s);
+        if (st != ROI_OK) return st;
+        lvl0[nf - 1] = out;
     }
     const float dc0 = dc_of(dt); // the frame's DC constant, also for denoised frames
     for (int l = 1; l < pl.L; ++l) {
@@ -810,7 +948,7 @@ roi_status roi_validate(int32_t h, int32_t w, roi_dtype dtype, const roi_params 
     if (!finite_pos(p->poly_sigma) || !finite_pos(p->eps)) return ROI_EINVAL;
     const roi_status ms = validate_mask_stage(p);
     if (ms == ROI_EINVAL) return ms;
-    if (p->flags & ~(uint32_t)(ROI_USE_INITIAL_FLOW | ROI_FP16_STORAGE)) return ROI_EINVAL;
+    if (p->flags & ~(uint32_t)(ROI_USE_INITIAL_FLOW | ROI_FP16_STORAGE | ROI_STABILIZE)) return ROI_EINVAL;
     if (p->denoise != 0 && p->denoise != 1) return ROI_EINVAL;
     if (p->adjacent < 0) return ROI_EINVAL;
     if (p->adjacent > ENS_MAX) return ROI_EUNSUPPORTED;
@@ -849,7 +987,7 @@ roi_status roi_mask(const void *prev, const void *next, int32_t h, int32_t w, in
     uint8_t *base = (uint8_t *)ws + HDR_BYTES;
     const void *frames[2] = {prev, next};
     const int sets[2] = {0, 1};
-    st = enqueue_expand(pl, base, 2, frames, pitch, dtype, p, sets, s);
+    st = enqueue_expand(pl, base, 2, frames, pitch, dtype, p, sets, s, phase_slot(ws, 0));
     if (st != ROI_OK) return st;
     return enqueue_flow(pl, base, (SelState *)ws, 0, 1, h, w, p, flow, mask, s);
 }
@@ -863,6 +1001,88 @@ roi_status roi_read_tau2(const void *ws, int32_t index, float *tau2_out, void *s
         return ROI_EDEVICE;
     std::memcpy(tau2_out, &sst.tau2_bits, 4);
     return ROI_OK;
+}
+
+roi_status roi_read_shift(const void *ws, int32_t index, int32_t *sy, int32_t *sx, float *peak, void *stream)
+{
+    if (!ws || !sy || !sx || index < 0 || index >= MAX_BATCH) return ROI_EINVAL;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return ROI_EDEVICE;
+    PhaseState ph;
+    if (hipMemcpy(&ph, phase_slot((void *)ws, index), sizeof ph, hipMemcpyDeviceToHost) != hipSuccess)
+        return ROI_EDEVICE;
+    *sy = ph.sy;
+    *sx = ph.sx;
+    if (peak) *peak = ph.peak;
+    return ROI_OK;
+}
+
+int32_t roi_phase_size(int32_t h, int32_t w) { return h < 0 || w < 0 ? 0 : phase_size(h, w); }
+
+// Workspace of roi_phase_correlation after the header: both frames as
+// floats and the registered frame (h rows of a 64-aligned pitch each), the
+// two complex fields, the tables and the argmax counters.
+struct PhasePlan {
+    int pitch;
+    size_t f[2], al, z, t, tw, hann, keys, bytes;
+};
+
+PhasePlan phase_plan(int h, int w)
+{
+    PhasePlan q{};
+    q.pitch = (int)align_up((size_t)w, 64);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off = align_up(off + b, ALIGN);
+        return o;
+    };
+    const size_t plane = (size_t)h * q.pitch * sizeof(float);
+    q.f[0] = take(plane);
+    q.f[1] = take(plane);
+    q.al = take(plane);
+    const size_t P = (size_t)phase_size(h, w);
+    q.z = take(P * P * sizeof(float2));
+    q.t = take(P * P * sizeof(float2));
+    q.tw = take(P / 2 * sizeof(float2) + sizeof(float2));
+    q.hann = take(P * sizeof(float));
+    q.keys = take(PH_SLOTS * PH_SLOT_STRIDE * sizeof(unsigned long long));
+    q.bytes = off;
+    return q;
+}
+
+size_t roi_phase_workspace_size(int32_t h, int32_t w)
+{
+    if (h < 0 || w < 0 || h > 32768 || w > 32768) return 0;
+    if (h == 0 || w == 0) return HDR_BYTES;
+    return HDR_BYTES + phase_plan(h, w).bytes;
+}
+
+roi_status roi_phase_correlation(const void *prev, const void *next, int32_t h, int32_t w, int64_t pitch,
+                                 roi_dtype dtype, float *surface, float *aligned, void *ws, size_t ws_bytes,
+                                 void *stream)
+{
+    if (h < 0 || w < 0) return ROI_EINVAL;
+    if (dtype != ROI_U8 && dtype != ROI_U16 && dtype != ROI_F32) return ROI_EINVAL;
+    if (h > 32768 || w > 32768) return ROI_EUNSUPPORTED;
+    if (h == 0 || w == 0) return ROI_OK;
+    if (!prev || !next || !ws || pitch < w || (uintptr_t)ws % ALIGN) return ROI_EINVAL;
+    const PhasePlan q = phase_plan(h, w);
+    if (ws_bytes < HDR_BYTES + q.bytes) return ROI_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *base = (uint8_t *)ws + HDR_BYTES;
+    float *f0 = (float *)(base + q.f[0]), *f1 = (float *)(base + q.f[1]);
+    to_float(dtype, prev, pitch, f0, q.pitch, h, w, s);
+    to_float(dtype, next, pitch, f1, q.pitch, h, w, s);
+    PhaseBufs b{};
+    b.P = phase_size(h, w);
+    b.z = (float2 *)(base + q.z);
+    b.t = (float2 *)(base + q.t);
+    b.tw = (float2 *)(base + q.tw);
+    b.hann = (float *)(base + q.hann);
+    b.keys = (unsigned long long *)(base + q.keys);
+    float *out = aligned ? aligned : (float *)(base + q.al);
+    return enqueue_phase(b, f0, f1, q.pitch, h, w, out, aligned ? w : q.pitch, phase_slot(ws, 0),
+                         b.P > 0 ? surface : nullptr, s);
 }
 
 // Workspace of roi_mask_from_flow after the header: m2 and sal (h rows of a
@@ -999,12 +1219,12 @@ size_t roi_batched_workspace_size(int32_t n, const roi_pair *pairs, roi_dtype dt
 }
 
 static roi_status enqueue_pair(const roi_pair &q, roi_dtype dtype, const roi_params *p, uint8_t *base,
-                               SelState *slot, hipStream_t s)
+                               SelState *slot, PhaseState *ph, hipStream_t s)
 {
     const Plan pl = make_plan(q.h, q.w, p);
     const void *frames[2] = {q.prev, q.next};
     const int sets[2] = {0, 1};
-    roi_status st = enqueue_expand(pl, base, 2, frames, q.pitch, dtype, p, sets, s);
+    roi_status st = enqueue_expand(pl, base, 2, frames, q.pitch, dtype, p, sets, s, ph);
     if (st != ROI_OK) return st;
     return enqueue_flow(pl, base, slot, 0, 1, q.h, q.w, p, q.flow, q.mask, s);
 }
@@ -1051,7 +1271,7 @@ roi_status roi_mask_batched(int32_t n, const roi_pair *pairs, roi_dtype dtype, c
         for (int i = 0; i < n && st == ROI_OK; ++i) {
             const roi_pair &q = pairs[i];
             if (q.h == 0 || q.w == 0) continue;
-            st = enqueue_pair(q, dtype, p, base, (SelState *)ws + i, ds->aux[i % naux]);
+            st = enqueue_pair(q, dtype, p, base, (SelState *)ws + i, phase_slot(ws, i), ds->aux[i % naux]);
             base += make_plan(q.h, q.w, p).bytes;
         }
         for (int k = 0; k < naux; ++k) {
@@ -1164,7 +1384,8 @@ static roi_status stream_push_one(roi_stream_ctx *c, const void *frame, int64_t 
     uint8_t *base = c->buf + HDR_BYTES;
     const void *frames[1] = {frame};
     const int sets[1] = {nxt};
-    roi_status st = enqueue_expand(c->plan, base, 1, frames, pitch, c->dtype, &c->p, sets, s);
+    roi_status st = enqueue_expand(c->plan, base, 1, frames, pitch, c->dtype, &c->p, sets, s, phase_slot(c->buf, 0),
+                                   c->primed ? c->cur : -1);
     if (st != ROI_OK) return st;
     if (!c->primed) {
         c->primed = 1;
@@ -1191,6 +1412,14 @@ static roi_status stream_push_one(roi_stream_ctx *c, const void *frame, int64_t 
         if (c->hist_count < K) c->hist_count += 1;
     }
     return ROI_OK;
+}
+
+roi_status roi_stream_read_shift(void *ctx, int32_t *sy, int32_t *sx, float *peak, void *stream)
+{
+    if (!ctx) return ROI_EINVAL;
+    roi_stream_ctx *c = (roi_stream_ctx *)ctx;
+    if (!(c->p.flags & ROI_STABILIZE)) return ROI_EINVAL;
+    return roi_read_shift(c->buf, 0, sy, sx, peak, stream);
 }
 
 roi_status roi_stream_push(void *ctx, const void *frame, int64_t pitch, float *flow, uint8_t *mask, void *stream)

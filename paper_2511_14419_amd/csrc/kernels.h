@@ -1455,6 +1455,196 @@ __global__ __launch_bounds__(256) void k_cc_compress(int32_t *lab, int32_t *link
         if (li[k] >= 0) lab[base + (ty + 4 * k) * w + tx] = groot[li[k]];
 }
 
+// ---------------------------------------------------------------- stabilisation
+
+// Phase correlation of two frames (the registration of a frame to its
+// predecessor): both frames are cut to the centred P x P window (P a power
+// of two, at most PH_MAXP), multiplied by the separable Hann window and
+// packed as one complex field z = a + i b, so one 2-D FFT transforms both.
+// The 2-D FFT is a row FFT, a transpose and a row FFT, so the spectrum is
+// held transposed (row kx, column ky). From Z(k) and Z(-k): A = Z + conj Z(-k)
+// and B = -i (Z - conj Z(-k)) (twice the spectra of a and b); the cross
+// power R = (B / |B|) conj(A / |A|) (0 where either is 0); its inverse FFT
+// (rows, transpose, rows: back in the frames' orientation) peaks at the
+// translation of b against a. The largest value (first in row-major order
+// on ties) is found with packed (value, index) keys and an atomic maximum
+// over spread counters.
+constexpr int PH_MAXP = 2048, PH_SLOTS = 64, PH_SLOT_STRIDE = 32; // 64-bit counters 256 bytes apart
+
+struct PhaseState { int32_t sy, sx; float peak; uint32_t valid; };
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+
+// twiddles tw[m] = exp(-2 pi i m / P) (m < P/2) and the Hann window
+// hann[i] = (1 - cos(2 pi i / (P - 1))) / 2, in double, rounded to float;
+// clears the argmax counters. grid: ceil((P/2 + P)/256) blocks, 256 threads
+__global__ __launch_bounds__(256) void k_ph_tables(float2 *tw, float *hann, unsigned long long *keys, int32_t P)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < P / 2) {
+        double sn, cs;
+        sincospi(-2.0 * (double)i / (double)P, &sn, &cs);
+        tw[i] = make_float2((float)cs, (float)sn);
+    } else if (i < P / 2 + P) {
+        const int j = i - P / 2;
+        hann[j] = (float)(0.5 - 0.5 * cospi(2.0 * (double)j / (double)(P - 1)));
+    }
+    if (blockIdx.x == 0 && threadIdx.x < PH_SLOTS) keys[threadIdx.x * PH_SLOT_STRIDE] = 0ull;
+}
+
+// level-0 frame of any input type as floats. grid: (ceil(w/64), ceil(h/4))
+template <typename TIn>
+__global__ __launch_bounds__(256) void k_to_float(const TIn *src, int64_t spitch, float *dst, int32_t dpitch,
+                                                  int32_t h, int32_t w)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x < w && y < h) dst[(size_t)y * dpitch + x] = (float)src[(size_t)y * spitch + x];
+}
+
+struct PhArgs {
+    const float *a, *b; int32_t pitch; // the two float frames
+    int32_t y0, x0, P;                 // the window
+    const float *hann;
+    float2 *z;                         // P x P
+};
+
+// z = hann(y) hann(x) (a + i b) over the window. grid: (P/64, P/4)
+__global__ __launch_bounds__(256) void k_ph_pack(PhArgs g)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= g.P || y >= g.P) return;
+    const size_t q = (size_t)(g.y0 + y) * g.pitch + g.x0 + x;
+    const float wgt = g.hann[y] * g.hann[x];
+    g.z[(size_t)y * g.P + x] = make_float2(wgt * g.a[q], wgt * g.b[q]);
+}
+
+// One radix-2 Stockham FFT per row of a P x P complex field, in LDS (two
+// P-point buffers; natural order in and out). INV: inverse with 1/P. LAST
+// (inverse only): instead of storing the row, the real parts go to `surface`
+// (nullable) and into the argmax keys. grid: P blocks, 256 threads, 2 P
+// float2 of dynamic LDS
+template <bool INV, bool LAST>
+__global__ __launch_bounds__(256) void k_fft_rows(float2 *data, int32_t P, const float2 *tw, float *surface,
+                                                  unsigned long long *keys)
+{
+    extern __shared__ float2 fsm[];
+    float2 *src = fsm, *dst = fsm + P;
+    float2 *row = data + (size_t)blockIdx.x * P;
+    for (int i = threadIdx.x; i < P; i += 256) src[i] = row[i];
+    __syncthreads();
+    const int half = P >> 1;
+    for (int Ns = 1; Ns < P; Ns <<= 1) {
+        const int step = half / Ns; // twiddle index stride: exp(-2 pi i k / (2 Ns)) = tw[k P / (2 Ns)]
+        for (int j = threadIdx.x; j < half; j += 256) {
+            const int k = j & (Ns - 1);
+            float2 t = tw[k * step];
+            if (INV) t.y = -t.y;
+            const float2 v0 = src[j], v1 = cmul(src[j + half], t);
+            const int d = ((j - k) << 1) + k;
+            dst[d] = make_float2(v0.x + v1.x, v0.y + v1.y);
+            dst[d + Ns] = make_float2(v0.x - v1.x, v0.y - v1.y);
+        }
+        __syncthreads();
+        float2 *tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    const float sc = INV ? 1.0f / (float)P : 1.0f;
+    if (!LAST) {
+        for (int i = threadIdx.x; i < P; i += 256) row[i] = make_float2(src[i].x * sc, src[i].y * sc);
+        return;
+    }
+    unsigned long long best = 0ull;
+    for (int i = threadIdx.x; i < P; i += 256) {
+        const float v = src[i].x * sc;
+        if (surface) surface[(size_t)blockIdx.x * P + i] = v;
+        const uint32_t b = __float_as_uint(v);
+        const uint32_t ord = (b & 0x80000000u) ? ~b : (b | 0x80000000u); // orders like the float
+        const uint32_t idx = (uint32_t)(blockIdx.x * P + i);
+        const unsigned long long key = ((unsigned long long)ord << 32) | (0xFFFFFFFFu - idx);
+        best = key > best ? key : best;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_xor(best, o, 64);
+        best = other > best ? other : best;
+    }
+    __shared__ unsigned long long red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = red[0];
+        for (int k = 1; k < 4; ++k) m = red[k] > m ? red[k] : m;
+        atomicMax(keys + (blockIdx.x % PH_SLOTS) * PH_SLOT_STRIDE, m);
+    }
+}
+
+// out = in^T for P x P complex fields, 32 x 32 tiles through LDS.
+// grid: (ceil(P/32), ceil(P/32)), 256 threads
+__global__ __launch_bounds__(256) void k_transpose(const float2 *in, float2 *out, int32_t P)
+{
+    __shared__ float2 t[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    for (int k = 0; k < 32; k += 8)
+        if (by + ty + k < P && bx + tx < P) t[ty + k][tx] = in[(size_t)(by + ty + k) * P + bx + tx];
+    __syncthreads();
+    for (int k = 0; k < 32; k += 8)
+        if (bx + ty + k < P && by + tx < P) out[(size_t)(bx + ty + k) * P + by + tx] = t[tx][ty + k];
+}
+
+// R(k) = (B / |B|) conj(A / |A|) from the transposed spectrum of z. grid: (P/64, P/4)
+__global__ __launch_bounds__(256) void k_ph_cross(const float2 *zt, float2 *rt, int32_t P)
+{
+    const int ky = blockIdx.x * 64 + (threadIdx.x & 63), kx = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (ky >= P || kx >= P) return;
+    const float2 Z = zt[(size_t)kx * P + ky];
+    const float2 M = zt[(size_t)((P - kx) & (P - 1)) * P + ((P - ky) & (P - 1))];
+    const float2 A = make_float2(Z.x + M.x, Z.y - M.y);          // Z + conj(M)
+    const float2 D = make_float2(Z.x - M.x, Z.y + M.y);          // Z - conj(M)
+    const float2 B = make_float2(D.y, -D.x);                     // -i D
+    const float na = __fmaf_rn(A.x, A.x, A.y * A.y), nb = __fmaf_rn(B.x, B.x, B.y * B.y);
+    float2 r = make_float2(0.0f, 0.0f);
+    if (na > 0.0f && nb > 0.0f) {
+        const float s = rsqrtf(na) * rsqrtf(nb);
+        r = make_float2((B.x * A.x + B.y * A.y) * s, (B.y * A.x - B.x * A.y) * s); // B conj(A) / (|A| |B|)
+    }
+    rt[(size_t)kx * P + ky] = r;
+}
+
+// The shift from the argmax keys (every block decodes it), then
+// dst(y, x) = src(y + sy, x + sx), coordinates clamped into the frame; block
+// (0, 0) records the shift (st nullable). P == 0: no estimate, zero shift.
+// grid: (ceil(w/64), ceil(h/4)), 256 threads
+__global__ __launch_bounds__(256) void k_ph_apply(const float *src, float *dst, int32_t pitch, int32_t dpitch,
+                                                  int32_t h, int32_t w, const unsigned long long *keys, int32_t P,
+                                                  PhaseState *st)
+{
+    int sy = 0, sx = 0;
+    float peak = 0.0f;
+    if (P > 0) {
+        unsigned long long k = keys[(threadIdx.x & 63) * PH_SLOT_STRIDE];
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long other = __shfl_xor(k, o, 64);
+            k = other > k ? other : k;
+        }
+        const uint32_t idx = 0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull);
+        const uint32_t ord = (uint32_t)(k >> 32);
+        peak = __uint_as_float((ord & 0x80000000u) ? (ord & 0x7FFFFFFFu) : ~ord);
+        const int py = (int)(idx / (uint32_t)P), px = (int)(idx % (uint32_t)P);
+        sy = py >= P / 2 ? py - P : py;
+        sx = px >= P / 2 ? px - P : px;
+    }
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (st && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        st->sy = sy;
+        st->sx = sx;
+        st->peak = peak;
+        st->valid = 1;
+    }
+    if (x < w && y < h)
+        dst[(size_t)y * dpitch + x] = src[(size_t)min(max(y + sy, 0), h - 1) * pitch + min(max(x + sx, 0), w - 1)];
+}
+
 // ---------------------------------------------------------------- adjacent-frame ensemble
 
 constexpr int ENS_MAX = 8;

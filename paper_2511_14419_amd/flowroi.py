@@ -20,12 +20,13 @@ ROI_OK, ROI_PRIMED, ROI_EINVAL, ROI_ENOMEM, ROI_EDEVICE, ROI_EUNSUPPORTED = 0, 1
 ROI_U8, ROI_U16, ROI_F32 = 0, 1, 2
 ROI_THRESH_ABS, ROI_THRESH_TOP = 0, 1
 ROI_SE_SQUARE, ROI_SE_DISC = 0, 1
-ROI_USE_INITIAL_FLOW, ROI_FP16_STORAGE = 1, 2
+ROI_USE_INITIAL_FLOW, ROI_FP16_STORAGE, ROI_STABILIZE = 1, 2, 4
 ROI_RULE_MAGNITUDE, ROI_RULE_SALIENCY = 0, 1
 
 EXPORTED = [
     "roi_default_params", "roi_validate", "roi_workspace_size", "roi_mask", "roi_read_tau2",
-    "roi_flow_mask_workspace_size", "roi_mask_from_flow",
+    "roi_flow_mask_workspace_size", "roi_mask_from_flow", "roi_read_shift", "roi_phase_size",
+    "roi_phase_workspace_size", "roi_phase_correlation", "roi_stream_read_shift",
     "roi_pyr_down", "roi_poly_expand", "roi_denoise", "roi_batched_workspace_size", "roi_mask_batched",
     "roi_stream_create", "roi_stream_push", "roi_stream_reset", "roi_stream_state_bytes",
     "roi_stream_destroy", "roi_stream_push_many", "roi_timing_enable", "roi_timing_read",
@@ -97,6 +98,18 @@ def lib():
         L.roi_flow_mask_workspace_size.restype = sz
         L.roi_mask_from_flow.argtypes = [vp, i32, i32, pp, vp, vp, vp, sz, vp]
         L.roi_mask_from_flow.restype = i32
+        L.roi_read_shift.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float),
+                                     vp]
+        L.roi_read_shift.restype = i32
+        L.roi_stream_read_shift.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                            ctypes.POINTER(ctypes.c_float), vp]
+        L.roi_stream_read_shift.restype = i32
+        L.roi_phase_size.argtypes = [i32, i32]
+        L.roi_phase_size.restype = i32
+        L.roi_phase_workspace_size.argtypes = [i32, i32]
+        L.roi_phase_workspace_size.restype = sz
+        L.roi_phase_correlation.argtypes = [vp, vp, i32, i32, i64, i32, vp, vp, vp, sz, vp]
+        L.roi_phase_correlation.restype = i32
         L.roi_pyr_down.argtypes = [vp, i32, i32, vp, vp]
         L.roi_pyr_down.restype = i32
         L.roi_poly_expand.argtypes = [vp, i32, i32, i64, i32, pp, vp, vp]
@@ -276,6 +289,42 @@ def mask_from_flow(flow, params=None, want_saliency=False, ws=None, stream=None,
     return mask, sal, ws
 
 
+def read_shift(ws, index=0, stream=None):
+    """(sy, sx, peak) of the last stabilised call on this workspace."""
+    sy, sx, pk = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0.0)
+    _check(lib().roi_read_shift(ctypes.c_void_p(ws.data_ptr()), index, ctypes.byref(sy), ctypes.byref(sx),
+                                ctypes.byref(pk), _stream(stream)), "roi_read_shift")
+    return sy.value, sx.value, pk.value
+
+
+def phase_size(h, w):
+    return lib().roi_phase_size(h, w)
+
+
+def phase_correlation(prev, next, want_surface=True, want_aligned=True, ws=None, stream=None):
+    """Stabilisation step alone on two device frames.
+
+    Returns (sy, sx, peak, surface (P, P) float32 or None, aligned (h, w) float32 or None)."""
+    if prev.shape != next.shape or prev.dtype != next.dtype or prev.stride() != next.stride():
+        raise ValueError("prev and next must share shape, dtype and strides")
+    h, w = prev.shape
+    dev = prev.device
+    P = phase_size(h, w)
+    surface = torch.empty((P, P), dtype=torch.float32, device=dev) if want_surface and P > 0 else None
+    aligned = torch.empty((h, w), dtype=torch.float32, device=dev) if want_aligned else None
+    need = lib().roi_phase_workspace_size(h, w)
+    if ws is None or ws.numel() < need:
+        ws = alloc_workspace(need, dev)
+    _check(lib().roi_phase_correlation(ctypes.c_void_p(prev.data_ptr()), ctypes.c_void_p(next.data_ptr()), h, w,
+                                       _frame_pitch(prev), dtype_code(prev.dtype),
+                                       ctypes.c_void_p(surface.data_ptr() if surface is not None else 0),
+                                       ctypes.c_void_p(aligned.data_ptr() if aligned is not None else 0),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+           "roi_phase_correlation")
+    sy, sx, pk = read_shift(ws, 0, stream)
+    return sy, sx, pk, surface, aligned
+
+
 def pyr_down(src, stream=None):
     h, w = src.shape
     dst = torch.empty(((h + 1) // 2, (w + 1) // 2), dtype=torch.float32, device=src.device)
@@ -346,6 +395,13 @@ class Stream:
                                             ctypes.c_void_p(flow.data_ptr() if flow is not None else 0),
                                             ctypes.c_void_p(mask.data_ptr() if mask is not None else 0),
                                             _stream(stream)), "roi_stream_push")
+
+    def read_shift(self, stream=None):
+        """(sy, sx, peak) that stabilisation applied to the last pushed frame."""
+        sy, sx, pk = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0.0)
+        _check(lib().roi_stream_read_shift(self.ctx, ctypes.byref(sy), ctypes.byref(sx), ctypes.byref(pk),
+                                           _stream(stream)), "roi_stream_read_shift")
+        return sy.value, sx.value, pk.value
 
     def reset(self):
         _check(lib().roi_stream_reset(self.ctx), "roi_stream_reset")

@@ -32,6 +32,14 @@ between frames. The recipes:
   "blobs": smoothed noise above its 70 % quantile; "snake": one 1-px wide
   path winding over the whole frame; "full"; "empty"; "dot": one pixel).
 
+* ``drifting_frames(h, w, drifts, seed)``: frames under global translational
+  drift, for the stabilisation stage. One canvas (background 1200, a
+  ``smooth_texture`` field of sigma 2 px and std 150, 200 * area / 2048^2
+  Gaussian-blob cells as in ``sequence_u16``) is cut at offsets that move by
+  the integer drifts, so frame t is frame t-1 moved by drifts[t-1]
+  (next(x) = prev(x - s)); independent Gaussian noise (sigma 25) per frame;
+  uint16, clipped to [0, 4095].
+
 All randomness comes from numpy's PCG64 generator seeded explicitly.
 """
 from __future__ import annotations
@@ -47,6 +55,7 @@ __all__ = [
     "smooth_texture",
     "flow_field",
     "binary_pattern",
+    "drifting_frames",
 ]
 
 # Blobs are rendered inside +-5 sigma; the Gaussian tail beyond is < 4e-6 of
@@ -195,3 +204,27 @@ def binary_pattern(h, w, kind, seed=0):
         m[h // 2, w // 2] = 1
         return m
     raise ValueError(kind)
+
+
+def drifting_frames(h, w, drifts, seed, noise_sigma=25.0):
+    """len(drifts) + 1 uint16 frames; frame t+1 is frame t moved by drifts[t]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cum = [(0, 0)]
+    for dy, dx in drifts:
+        cum.append((cum[-1][0] + int(dy), cum[-1][1] + int(dx)))
+    pad_y = max(abs(c[0]) for c in cum) + 1
+    pad_x = max(abs(c[1]) for c in cum) + 1
+    H, W = h + 2 * pad_y, w + 2 * pad_x
+    canvas = 1200.0 + smooth_texture(H, W, seed + 1, sigma=2.0, amplitude=150.0, pad=0)
+    n_blobs = max(1, int(200 * H * W / 2048 ** 2))
+    sig = rng.uniform(5, 10, n_blobs)
+    cen = np.stack([rng.uniform(0, H, n_blobs), rng.uniform(0, W, n_blobs)], 1)
+    amp = rng.uniform(375, 750, n_blobs)
+    canvas = canvas + render_frame(H, W, 0.0, 0.0, cen, sig, amp, rng)
+    out = []
+    for cy, cx in cum:
+        # frame(x) = canvas(x - c + pad): moving the cut by -c moves the content by +c
+        f = canvas[pad_y - cy:pad_y - cy + h, pad_x - cx:pad_x - cx + w]
+        f = f + rng.normal(0.0, noise_sigma, (h, w))
+        out.append(np.clip(np.rint(f), 0, 4095).astype(np.uint16))
+    return np.stack(out)

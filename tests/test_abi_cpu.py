@@ -89,6 +89,9 @@ def test_defaults(F):
     ({"rule": 1, "morph_radius": 3}, 64, 64, 0, -4),
     ({"rule": 1, "min_area": -2}, 64, 64, 0, -1),
     ({"rule": 0, "morph_radius": 7, "min_area": -2}, 64, 64, 0, 0),
+    ({"flags": 4}, 64, 64, 1, 0),
+    ({"flags": 7}, 64, 64, 1, 0),
+    ({"flags": 12}, 64, 64, 1, -1),
 ])
 def test_validate(F, kw, h, w, dtype, expect):
     assert F.validate(h, w, dtype, F.default_params(**kw)) == expect
@@ -142,6 +145,28 @@ def test_mask_from_flow_rejects_before_launch(F):
     bad = F.default_params(rule=1, morph_radius=3)
     assert L.roi_mask_from_flow(fake, 64, 64, ctypes.byref(bad), fake, None, ws, 1 << 30, None) == F.ROI_EUNSUPPORTED
     assert L.roi_mask_from_flow(None, 0, 64, ctypes.byref(p), None, None, None, 0, None) == F.ROI_OK
+
+
+def test_phase_sizes_and_rejections(F):
+    L = F.lib()
+    assert [F.phase_size(h, w) for h, w in [(2048, 2448), (1536, 1536), (5, 300), (1, 300), (3000, 3000), (2, 2)]] \
+        == [2048, 1024, 4, 0, 2048, 2]
+    p = F.default_params()
+    s = F.default_params(flags=F.ROI_STABILIZE)
+    assert L.roi_workspace_size(512, 512, 1, ctypes.byref(s)) > L.roi_workspace_size(512, 512, 1, ctypes.byref(p))
+    need = L.roi_phase_workspace_size(256, 300)
+    assert need > L.roi_phase_workspace_size(0, 300) > 0
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x100000)
+    assert L.roi_phase_correlation(None, fake, 256, 300, 300, 1, None, None, ws, need, None) == F.ROI_EINVAL
+    assert L.roi_phase_correlation(fake, fake, 256, 300, 299, 1, None, None, ws, need, None) == F.ROI_EINVAL
+    assert L.roi_phase_correlation(fake, fake, 256, 300, 300, 5, None, None, ws, need, None) == F.ROI_EINVAL
+    assert L.roi_phase_correlation(fake, fake, 256, 300, 300, 1, None, None, ws, need - 1, None) == F.ROI_ENOMEM
+    assert L.roi_phase_correlation(None, None, 0, 300, 300, 1, None, None, None, 0, None) == F.ROI_OK
+    i = ctypes.c_int32()
+    assert L.roi_read_shift(None, 0, ctypes.byref(i), ctypes.byref(i), None, None) == F.ROI_EINVAL
+    assert L.roi_read_shift(ws, 256, ctypes.byref(i), ctypes.byref(i), None, None) == F.ROI_EINVAL
+    assert L.roi_stream_read_shift(None, ctypes.byref(i), ctypes.byref(i), None, None) == F.ROI_EINVAL
 
 
 def test_batched_and_stream_reject_before_launch(F):
