@@ -10,12 +10,15 @@ per consecutive pair with the default parameters (3 levels, 15x15 window,
 A step is one pass over the 63 pairs; `value` is pairs (= output frames)
 per second with every frame already resident in HBM.
 
-Beside it the JSON line carries the streaming path (previous frame's
-expansion kept resident), the batched path (16 lens streams of uneven
-sizes in one graph launch, FP32 and FP16 storage), per-pair latency
-percentiles, the roofline of the dominant kernel (the iteration kernel,
-timed with HIP events on its own stream inside the timed region) and the
-FP64 oracle timed on the host on one 2048x2048 pair.
+Beside it the JSON line carries the plain path with the other stages
+switched on (denoising, the saliency rule, a top-fraction threshold,
+stabilisation), the mask stage alone per rule, the streaming path (previous
+frame's expansion kept resident; with the adjacent-frame ensemble), the
+batched path (16 lens streams of uneven sizes in one graph launch, FP32 and
+FP16 storage), the serving sweep, per-pair latency percentiles, the roofline
+of the dominant kernel (the iteration kernel, timed with HIP events on its
+own stream inside the timed region) and the FP64 oracle timed on the host
+on one 2048x2048 pair.
 
 Progress goes to stderr; stdout gets exactly one JSON line.
 """
@@ -88,8 +91,11 @@ def main():
     torch.cuda.synchronize()
 
     log("timed %d steps x %d pairs" % (args.steps, npairs))
+    # iteration-kernel time inside the timed region: one pair of HIP events
+    # around each call's 9 back-to-back iteration launches (the event pool is
+    # filled before the clock starts)
+    fl.timing_enable(True, per_call=True)
     fl.timing_reset()
-    fl.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -98,7 +104,15 @@ def main():
     t1 = time.perf_counter()
     fl.timing_enable(False)
     k_ms, k_n, k_px, k_bytes = fl.timing_read()
+    # per-level breakdown: one more step, outside the timed region, with
+    # events around every launch
+    fl.timing_reset()
+    fl.timing_enable(True)
+    step()
+    torch.cuda.synchronize()
+    fl.timing_enable(False)
     recs = fl.timing_records()
+    fl.timing_reset()
     per_level = {}
     for ms_, px_, b_ in recs:
         e = per_level.setdefault(px_, [0.0, 0.0, 0])
@@ -171,6 +185,9 @@ def main():
         out["plain_top_fraction"] = bench_plain_variant(fl, frames, flows, masks, dev, args,
                                                         fl.default_params(thresh_mode=1, thresh=0.2),
                                                         "magnitude rule, top 20 % of |d|")
+        out["plain_stabilized"] = bench_plain_variant(fl, frames, flows, masks, dev, args,
+                                                      fl.default_params(flags=fl.ROI_STABILIZE),
+                                                      "stabilisation on (phase correlation over 2048x2048)")
         out["mask_stage_us"] = bench_mask_stage(fl, flows[0], args)
         out["streaming"] = bench_streaming(fl, frames, p, dev, args)
         out["streaming_adjacent2"] = bench_streaming(fl, frames, fl.default_params(adjacent=2), dev, args)

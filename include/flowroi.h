@@ -365,21 +365,28 @@ void roi_server_destroy(void *srv);
 
 /* ---- Kernel timing ------------------------------------------------------ */
 
-/* When enabled, the library records HIP events around every launch of the
- * iteration kernel (warp + update + window + solve, the dominant kernel) on
- * the stream it is launched on. roi_timing_read synchronises those events
- * and returns, summed since the last reset: kernel time (ms), launches,
- * output pixels, and algorithmic bytes (expansion planes of both frames at
- * the storage width + prior flow read + flow written + |d|^2 written, each
- * counted once per output pixel). Launches captured into graphs are not
- * timed. */
-void roi_timing_enable(int32_t on);
+/* Timing of the iteration kernel (warp + update + window + solve, the
+ * dominant kernel) with HIP events on the stream it is launched on.
+ * mode 1: events around every launch; mode 2: one pair of events around
+ * each call's run of iteration launches (they are back to back on the
+ * stream, so the bracket is their kernel time plus the dispatch gaps
+ * between them, and the call records far fewer events); 0: off. Events come
+ * from a pool that roi_timing_read refills; mode 1 or 2 pre-creates `ROI_
+ * TIMING_POOL` of them when the pool is smaller. roi_timing_read
+ * synchronises the pending events and returns, summed since the last reset:
+ * kernel time (ms), launches, output pixels, and algorithmic bytes
+ * (expansion planes of both frames at the storage width + prior flow read +
+ * flow written + the mask stage's input written, each counted once per
+ * output pixel). Launches captured into graphs are not timed. */
+#define ROI_TIMING_POOL 4096
+void roi_timing_enable(int32_t mode);
 roi_status roi_timing_read(double *total_ms, int64_t *launches, int64_t *pixels, double *bytes);
 void roi_timing_reset(void);
 
-/* Per-launch records behind roi_timing_read (same synchronisation): fills
- * up to `max` entries of kernel ms, output pixels and algorithmic bytes, in
- * launch order, and returns the number of records available. */
+/* Records behind roi_timing_read (same synchronisation): fills up to `max`
+ * entries of kernel ms, output pixels and algorithmic bytes, one per launch
+ * (mode 1) or per call (mode 2), in order, and returns the number of
+ * records available. */
 int32_t roi_timing_records(double *ms, int64_t *pixels, double *bytes, int32_t max);
 
 /* ---- Tuning -------------------------------------------------------------- */

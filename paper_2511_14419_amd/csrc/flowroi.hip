@@ -131,7 +131,7 @@ Plan make_plan(int h, int w, const roi_params *p)
         const size_t P = (size_t)pl.ph_P;
         pl.ph_z = take(P * P * sizeof(float2));
         pl.ph_t = take(P * P * sizeof(float2));
-        pl.ph_tw = take(P / 2 * sizeof(float2) + sizeof(float2));
+        pl.ph_tw = take(P * sizeof(float2));
         pl.ph_hann = take(P * sizeof(float));
         pl.ph_keys = take(PH_SLOTS * PH_SLOT_STRIDE * sizeof(unsigned long long));
     }
@@ -151,11 +151,12 @@ struct TimedLaunch {
     hipEvent_t e0, e1;
     int64_t px;
     double bytes;
+    int32_t n; // launches inside the bracket
 };
 
 struct Timing {
     std::mutex mu;
-    bool on = false;
+    int mode = 0; // 0 off, 1 per launch, 2 per call
     std::vector<TimedLaunch> pending;
     std::vector<hipEvent_t> pool;
     double done_ms = 0, done_bytes = 0;
@@ -252,8 +253,11 @@ void launch_poly(const PolyArgs &a, int frames, hipStream_t s)
 {
     // packed output also covers the zero padding columns and the zero row below the frame
     const int cols = a.packed ? a.dpitch : a.w;
-    dim3 g((cols + PE_TW - 1) / PE_TW, (a.h + (a.packed ? 1 : 0) + PE_TH - 1) / PE_TH, frames);
-    hipLaunchKernelGGL((k_polyexp<TIn, TOut>), g, dim3(256), 0, s, a);
+    dim3 g((cols + PE_TW - 1) / PE_TW, (a.h + (a.packed ? 1 : 0) + PE_TH2 - 1) / PE_TH2, frames);
+    const dim3 b(PE_THREADS);
+    if (a.n == 1) hipLaunchKernelGGL((k_polyexp<TIn, TOut, 1>), g, b, 0, s, a);
+    else if (a.n == 2) hipLaunchKernelGGL((k_polyexp<TIn, TOut, 2>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_polyexp<TIn, TOut, 3>), g, b, 0, s, a);
 }
 
 template <typename TOut>
@@ -345,7 +349,7 @@ roi_status enqueue_phase(const PhaseBufs &b, const float *ref, const float *mov,
 {
     const int P = b.P;
     if (P > 0) {
-        hipLaunchKernelGGL(k_ph_tables, dim3((P / 2 + P + 255) / 256), dim3(256), 0, s, b.tw, b.hann, b.keys, P);
+        hipLaunchKernelGGL(k_ph_tables, dim3((2 * P + 255) / 256), dim3(256), 0, s, b.tw, b.hann, b.keys, P);
         PhArgs g{};
         g.a = ref;
         g.b = mov;
@@ -554,6 +558,7 @@ double iter_bytes(const IterArgs &a, bool fp16)
     if (a.prior == PRIOR_PLAIN) b += px * sizeof(float2);
     if (a.prior == PRIOR_UPSAMPLE) b += (double)a.hc * a.wc * sizeof(float2);
     if (a.m2) b += px * sizeof(float);
+    if (a.pre8) b += px;
     return b;
 }
 
@@ -594,35 +599,59 @@ int choose_strip(const IterArgs &a, bool fp16, hipStream_t s)
     return best;
 }
 
-roi_status launch_iter(const IterArgs &a, bool fp16, hipStream_t s)
-{
-    const int strip = choose_strip(a, fp16, s);
+// An open timing bracket: events recorded on `s` at open and close when the
+// timing mode is `mode` and the stream is not being captured.
+struct Bracket {
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipStream_t s = nullptr;
+    int64_t px = 0;
+    double bytes = 0;
+    int32_t n = 0;
+
+    void open(int mode, hipStream_t st)
     {
-        std::lock_guard<std::mutex> lk(g_timing.mu);
-        if (g_timing.on && !capturing(s)) {
+        s = st;
+        {
+            std::lock_guard<std::mutex> lk(g_timing.mu);
+            if (g_timing.mode != mode || capturing(st)) return;
             e0 = g_timing.get();
             e1 = g_timing.get();
         }
+        if (e0 && e1) hipEventRecord(e0, s);
     }
-    const bool timed = e0 && e1;
-    if (timed) hipEventRecord(e0, s);
+    void close()
+    {
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        if (e0 && e1 && n > 0) {
+            hipEventRecord(e1, s);
+            g_timing.pending.push_back({e0, e1, px, bytes, n});
+        } else {
+            if (e0) g_timing.pool.push_back(e0);
+            if (e1) g_timing.pool.push_back(e1);
+        }
+        e0 = e1 = nullptr;
+    }
+};
+
+roi_status launch_iter(const IterArgs &a, bool fp16, hipStream_t s, Bracket *call)
+{
+    const int strip = choose_strip(a, fp16, s);
+    Bracket one;
+    one.open(1, s);
     launch_iter_raw(a, fp16, strip, s);
     const bool ok = hipGetLastError() == hipSuccess;
-    if (timed) {
-        hipEventRecord(e1, s);
-        std::lock_guard<std::mutex> lk(g_timing.mu);
-        g_timing.pending.push_back({e0, e1, (int64_t)a.h * a.w, iter_bytes(a, fp16)});
-    } else {
-        std::lock_guard<std::mutex> lk(g_timing.mu);
-        if (e0) g_timing.pool.push_back(e0);
-        if (e1) g_timing.pool.push_back(e1);
+    one.px = (int64_t)a.h * a.w;
+    one.bytes = iter_bytes(a, fp16);
+    one.n = 1;
+    one.close();
+    if (call) {
+        call->px += (int64_t)a.h * a.w;
+        call->bytes += iter_bytes(a, fp16);
+        call->n += 1;
     }
     return ok ? ROI_OK : ROI_EDEVICE;
 }
 
-// Coarse-to-fine iterations from expansion set `s1` (prev) to `s2` (next),
-// then the threshold and dilation into `mask` (skipped when mask is NULL).
 // Buffers of the stage from |d|^2 to the mask. m2 (pitch m2_pitch) holds
 // |d|^2; under the saliency rule sal (h rows of sal_pitch floats), lab and
 // area (h w int32 each) are scratch, and the component links reuse m2.
@@ -635,6 +664,7 @@ struct MaskBufs {
     int32_t *lab;
     int32_t *area;
     uint32_t *maxs; // 3 MAXSLOT_WORDS counters: max M, max G, max S
+    bool pre8;      // m2 holds the pre-mask bytes (pitch w) of an absolute threshold, already recorded
 };
 
 void launch_select(const float *v, int pitch, int h, int w, const roi_params *p, SelState *slot, uint32_t *hist,
@@ -662,7 +692,9 @@ roi_status enqueue_mask(const MaskBufs &mb, SelState *slot, int h, int w, const 
     d.m2 = mb.m2;
     d.m2_pitch = mb.m2_pitch;
     d.st = slot;
-    if (p->rule == ROI_RULE_MAGNITUDE) {
+    if (p->rule == ROI_RULE_MAGNITUDE && mb.pre8) {
+        d.pre8 = (const uint8_t *)mb.m2;
+    } else if (p->rule == ROI_RULE_MAGNITUDE) {
         if (p->thresh_mode == ROI_THRESH_ABS) {
             const float t2 = p->thresh * p->thresh;
             uint32_t bits;
@@ -740,24 +772,34 @@ roi_status enqueue_mask(const MaskBufs &mb, SelState *slot, int h, int w, const 
         }
         d.hw[u + d.r] = (int8_t)hw;
     }
-    dim3 g((w + DIL_TW - 1) / DIL_TW, (h + DIL_TH - 1) / DIL_TH);
-    switch (d.r) {
-    case 0: hipLaunchKernelGGL(k_dilate<0>, g, dim3(256), 0, s, d); break;
-    case 1: hipLaunchKernelGGL(k_dilate<1>, g, dim3(256), 0, s, d); break;
-    case 2: hipLaunchKernelGGL(k_dilate<2>, g, dim3(256), 0, s, d); break;
-    case 3: hipLaunchKernelGGL(k_dilate<3>, g, dim3(256), 0, s, d); break;
-    case 4: hipLaunchKernelGGL(k_dilate<4>, g, dim3(256), 0, s, d); break;
-    default: hipLaunchKernelGGL(k_dilate<-1>, g, dim3(256), 0, s, d); break;
+    if (d.r <= DB_MAXR) {
+        const dim3 g((w + DIL_TW - 1) / DIL_TW, (h + DB_TH - 1) / DB_TH);
+        if (d.lab) hipLaunchKernelGGL(k_dilate_bits<2>, g, dim3(256), 0, s, d);
+        else if (d.pre8) hipLaunchKernelGGL(k_dilate_bits<1>, g, dim3(256), 0, s, d);
+        else hipLaunchKernelGGL(k_dilate_bits<0>, g, dim3(256), 0, s, d);
+    } else {
+        const dim3 g((w + DIL_TW - 1) / DIL_TW, (h + DIL_TH - 1) / DIL_TH);
+        hipLaunchKernelGGL(k_dilate<-1>, g, dim3(256), 0, s, d);
     }
     LAUNCH_CHECK();
     return ROI_OK;
 }
 
+// Coarse-to-fine iterations from expansion set `s1` (prev) to `s2` (next),
+// then the threshold and dilation into `mask` (skipped when mask is NULL).
 roi_status enqueue_flow(const Plan &pl, uint8_t *base, SelState *slot, int s1, int s2, int h, int w,
                         const roi_params *p, float *flow, uint8_t *mask, hipStream_t s)
 {
     const bool init = (p->flags & ROI_USE_INITIAL_FLOW) != 0;
     const int L = pl.L, n = p->iterations;
+    // an absolute threshold on |d| is known before the flow: the last update
+    // writes the pre-mask bytes and records the threshold itself
+    const bool pre8_mode = p->rule == ROI_RULE_MAGNITUDE && p->thresh_mode == ROI_THRESH_ABS;
+    uint32_t t2bits = 0;
+    {
+        const float t2 = p->thresh * p->thresh;
+        std::memcpy(&t2bits, &t2, 4);
+    }
     const Level &c = pl.lv[L - 1];
     if (init) {
         InitArgs a{};
@@ -776,6 +818,8 @@ roi_status enqueue_flow(const Plan &pl, uint8_t *base, SelState *slot, int s1, i
     }
     const float2 *coarse = nullptr;
     int coarse_pitch = 0, hc = 0, wc = 0;
+    Bracket call; // timing mode 2: the call's run of iteration launches
+    call.open(2, s);
     for (int l = L - 1; l >= 0; --l) {
         const Level &v = pl.lv[l];
         float2 *X = (float2 *)(base + v.fa);
@@ -815,11 +859,20 @@ roi_status enqueue_flow(const Plan &pl, uint8_t *base, SelState *slot, int s1, i
             a.R = p->winsize / 2;
             a.eps = p->eps;
             if (l == 0 && it == n - 1 && mask) {
-                a.m2 = (float *)(base + pl.m2_off);
-                a.m2_pitch = pl.lv[0].pitch;
+                if (pre8_mode) {
+                    a.pre8 = base + pl.m2_off;
+                    a.t2bits = t2bits;
+                    a.st = slot;
+                } else {
+                    a.m2 = (float *)(base + pl.m2_off);
+                    a.m2_pitch = pl.lv[0].pitch;
+                }
             }
-            roi_status st = launch_iter(a, pl.fp16, s);
-            if (st != ROI_OK) return st;
+            roi_status st = launch_iter(a, pl.fp16, s, &call);
+            if (st != ROI_OK) {
+                call.close();
+                return st;
+            }
             prev_out = a.fout;
             prev_pitch = a.fout_pitch;
         }
@@ -828,6 +881,7 @@ roi_status enqueue_flow(const Plan &pl, uint8_t *base, SelState *slot, int s1, i
         hc = v.h;
         wc = v.w;
     }
+    call.close();
     if (!mask) return ROI_OK;
     MaskBufs mb{};
     mb.m2 = (float *)(base + pl.m2_off);
@@ -840,6 +894,7 @@ roi_status enqueue_flow(const Plan &pl, uint8_t *base, SelState *slot, int s1, i
     mb.lab = (int32_t *)(base + pl.lv[0].fa + (size_t)pl.lv[0].h * pl.lv[0].pitch * sizeof(float));
     mb.area = (int32_t *)(base + pl.area_off);
     mb.maxs = (uint32_t *)(base + pl.max_off);
+    mb.pre8 = pre8_mode;
     return enqueue_mask(mb, slot, h, w, p, mask, nullptr, s);
 }
 
@@ -1043,7 +1098,7 @@ PhasePlan phase_plan(int h, int w)
     const size_t P = (size_t)phase_size(h, w);
     q.z = take(P * P * sizeof(float2));
     q.t = take(P * P * sizeof(float2));
-    q.tw = take(P / 2 * sizeof(float2) + sizeof(float2));
+    q.tw = take(P * sizeof(float2));
     q.hann = take(P * sizeof(float));
     q.keys = take(PH_SLOTS * PH_SLOT_STRIDE * sizeof(unsigned long long));
     q.bytes = off;
@@ -1453,10 +1508,16 @@ roi_status roi_stream_push_many(int32_t n, void *const *ctxs, const void *const 
 
 // ---------------------------------------------------------------- timing
 
-void roi_timing_enable(int32_t on)
+void roi_timing_enable(int32_t mode)
 {
     std::lock_guard<std::mutex> lk(g_timing.mu);
-    g_timing.on = on != 0;
+    g_timing.mode = mode == 1 || mode == 2 ? mode : 0;
+    // event creation is far slower than a record: fill the pool up front
+    while (g_timing.mode && g_timing.pool.size() < ROI_TIMING_POOL) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) break;
+        g_timing.pool.push_back(e);
+    }
 }
 
 roi_status roi_timing_read(double *total_ms, int64_t *launches, int64_t *pixels, double *bytes)
@@ -1467,7 +1528,7 @@ roi_status roi_timing_read(double *total_ms, int64_t *launches, int64_t *pixels,
         float ms = 0;
         if (hipEventElapsedTime(&ms, t.e0, t.e1) != hipSuccess) return ROI_EDEVICE;
         g_timing.done_ms += ms;
-        g_timing.done_n += 1;
+        g_timing.done_n += t.n;
         g_timing.done_px += t.px;
         g_timing.done_bytes += t.bytes;
         g_timing.rec_ms.push_back(ms);

@@ -115,10 +115,14 @@ template <> struct Packed<__half> {
 // FP16 rounding of a value kept in an FP32 buffer (stage entry points).
 __device__ __forceinline__ float round16(float v) { return __half2float(__float2half(v)); }
 
+// Threshold state of one pair (the radix select's progress; the applied
+// threshold's float bits).
+struct SelState { uint32_t prefix, rank, tau2_bits, pad; };
+
 // ---------------------------------------------------------------- pyramid
 
-constexpr int PYR_TW = 64, PYR_TH = 8;
-constexpr int PYR_SW = 2 * PYR_TW + 3, PYR_SH = 2 * PYR_TH + 3;
+constexpr int PYR_TW = 62, PYR_TH = 16; // 2 x 62 + 3 = 127 input columns: one vertical job per thread
+constexpr int PYR_SW = 2 * PYR_TW + 3, PYR_SH = 2 * PYR_TH + 3; // input columns / rows per tile
 
 struct PyrArgs {
     const void *src[2];
@@ -134,35 +138,58 @@ struct PyrArgs {
 // accumulated in FP64: pyramid images keep the frame's full dynamic range,
 // and FP32 rounding of values far from zero feeds straight into the
 // derivative filters of the expansion.
-// grid: (ceil(w2/64), ceil(h2/8), frames)
+// Vertical pass straight from global memory: a job is one input column and
+// one half of the tile's output rows (19 input rows, loaded together), its
+// vertical sums go to LDS; in the horizontal pass the lanes take
+// consecutive output columns, so stores write whole row segments.
+// grid: (ceil(w2/62), ceil(h2/16), frames), 256 threads
 template <typename TIn, typename TOut>
 __global__ __launch_bounds__(256) void k_pyr_down(PyrArgs a)
 {
-    __shared__ double s[PYR_SH][PYR_SW + 1];
-    __shared__ double v[PYR_TH][PYR_SW + 1];
+    constexpr int JOBS = 2 * PYR_SW, ROWS = PYR_TH / 2, IN = 2 * ROWS + 3;
+    static_assert(JOBS <= 256, "one vertical job per thread");
+    constexpr int NE = (PYR_SW + 1) / 2, NO = PYR_SW / 2; // even / odd input columns
+    // vertical sums kept by column parity: output column c needs even
+    // columns c, c+1, c+2 and odd columns c, c+1, so lanes over c read
+    // consecutive doubles (the odd array starts one double later to keep
+    // the two arrays' banks apart)
+    __shared__ double ve[PYR_TH][NE];
+    __shared__ double vo[PYR_TH][NO + 1];
     const TIn *src = (const TIn *)a.src[blockIdx.z];
     TOut *dst = (TOut *)a.dst[blockIdx.z];
     const int ox0 = blockIdx.x * PYR_TW, oy0 = blockIdx.y * PYR_TH;
     const int sx0 = 2 * ox0 - 2, sy0 = 2 * oy0 - 2;
-    for (int i = threadIdx.x; i < PYR_SH * PYR_SW; i += 256) {
-        const int r = i / PYR_SW, c = i - r * PYR_SW;
-        const int y = clampi(sy0 + r, 0, a.h - 1), x = clampi(sx0 + c, 0, a.w - 1);
-        s[r][c] = ldd(src, (size_t)y * a.src_pitch + x) - (double)a.dc;
-    }
-    __syncthreads();
     const double k0 = 1.0 / 16, k1 = 4.0 / 16, k2 = 6.0 / 16;
-    for (int i = threadIdx.x; i < PYR_TH * PYR_SW; i += 256) {
-        const int r = i / PYR_SW, c = i - r * PYR_SW;
-        const int b = 2 * r;
-        v[r][c] = k0 * s[b][c] + k1 * s[b + 1][c] + k2 * s[b + 2][c] + k1 * s[b + 3][c] + k0 * s[b + 4][c];
+    double f[IN];
+    const int j = min((int)threadIdx.x, JOBS - 1);
+    const int cj = j % PYR_SW, half = j / PYR_SW;
+    {
+        const int x = clampi(sx0 + cj, 0, a.w - 1);
+#pragma unroll
+        for (int i = 0; i < IN; ++i) {
+            const int y = clampi(sy0 + 2 * ROWS * half + i, 0, a.h - 1);
+            f[i] = ldd(src, (size_t)y * a.src_pitch + x) - (double)a.dc;
+        }
+    }
+    if ((int)threadIdx.x < JOBS) {
+        double *col = (cj & 1) ? &vo[0][1 + (cj >> 1)] : &ve[0][cj >> 1];
+        const int stride = (cj & 1) ? NO + 1 : NE;
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int b = 2 * r;
+            col[(ROWS * half + r) * stride] =
+                k0 * f[b] + k1 * f[b + 1] + k2 * f[b + 2] + k1 * f[b + 3] + k0 * f[b + 4];
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < PYR_TH * PYR_TW; i += 256) {
-        const int r = i / PYR_TW, c = i - r * PYR_TW;
-        const int y = oy0 + r, x = ox0 + c;
-        if (y >= a.h2 || x >= a.w2) continue;
-        const int b = 2 * c;
-        double o = k0 * v[r][b] + k1 * v[r][b + 1] + k2 * v[r][b + 2] + k1 * v[r][b + 3] + k0 * v[r][b + 4];
+    // horizontal pass: lane = output column, rows (t >> 6) + 4 i
+    const int c = threadIdx.x & 63, x = ox0 + c;
+    if (c >= PYR_TW || x >= a.w2) return;
+#pragma unroll
+    for (int i = 0; i < PYR_TH / 4; ++i) {
+        const int r = (threadIdx.x >> 6) + 4 * i, y = oy0 + r;
+        if (y >= a.h2) break;
+        double o = k0 * ve[r][c] + k1 * vo[r][1 + c] + k2 * ve[r][c + 1] + k1 * vo[r][2 + c] + k0 * ve[r][c + 2];
         if (a.round16) o = (double)round16((float)o);
         std_(dst, (size_t)y * a.dst_pitch + x, o);
     }
@@ -313,67 +340,114 @@ struct PolyArgs {
 // The expansion's derivative filters cancel the (large) local mean of the
 // image, so the fit runs in FP64 arithmetic; only the stored coefficients
 // are rounded to the storage type.
-// grid: (ceil(w/64), ceil(h/16), frames)
-template <typename TIn, typename TOut>
-__global__ __launch_bounds__(256) void k_polyexp(PolyArgs a)
+// Vertical pass straight from global memory: a job (one per thread) is one
+// input column and a quarter (8 rows) of the 64 x 32 tile's output rows, its
+// 8 + 2N input rows loaded together; the three vertical sums go to LDS.
+// Horizontal pass: lanes over the columns of a row, 4 rows per thread. The filters are symmetric or
+// antisymmetric, so they run on sums and differences of mirrored taps.
+// grid: (ceil(cols/64), ceil(rows/32), frames), 512 threads; N = poly_n / 2
+constexpr int PE_TH2 = 32;
+
+// Symmetric (even) and antisymmetric (odd) 2N+1-tap kernels on a window x
+// centred at x[N]: even = e[N] x[N] + sum_j e[N+j] (x[N+j] + x[N-j]),
+// odd = sum_j o[N+j] (x[N+j] - x[N-j]).
+template <int N>
+__device__ __forceinline__ void sym_sums(const double *x, double *s, double *d)
 {
-    constexpr int SW = PE_TW + 2 * PE_MAXN, SH = PE_TH + 2 * PE_MAXN;
-    __shared__ double s[SH][SW + 1];
-    __shared__ double vr[3][PE_TH][SW + 1];
+#pragma unroll
+    for (int j = 1; j <= N; ++j) {
+        s[j] = x[N + j] + x[N - j];
+        d[j] = x[N + j] - x[N - j];
+    }
+}
+
+template <int N>
+__device__ __forceinline__ double even_tap(const double *e, double x0, const double *s)
+{
+    double r = e[N] * x0;
+#pragma unroll
+    for (int j = 1; j <= N; ++j) r += e[N + j] * s[j];
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ double odd_tap(const double *o, const double *d)
+{
+    double r = o[N + 1] * d[1];
+#pragma unroll
+    for (int j = 2; j <= N; ++j) r += o[N + j] * d[j];
+    return r;
+}
+
+constexpr int PE_THREADS = 512;
+
+template <typename TIn, typename TOut, int N>
+__global__ __launch_bounds__(PE_THREADS) void k_polyexp(PolyArgs a)
+{
+    // SW + 1 is odd for every N: the horizontal pass's lanes read 32 rows at
+    // once without bank conflicts
+    constexpr int SW = PE_TW + 2 * N, JOBS = 4 * SW, ROWS = PE_TH2 / 4, IN = ROWS + 2 * N;
+    __shared__ double vr[3][PE_TH2][SW + 1];
     const TIn *src = (const TIn *)a.src[blockIdx.z];
-    const int n = a.n, sw = PE_TW + 2 * n, sh = PE_TH + 2 * n;
-    const int ox0 = blockIdx.x * PE_TW, oy0 = blockIdx.y * PE_TH;
-    for (int i = threadIdx.x; i < sh * sw; i += 256) {
-        const int r = i / sw, c = i - r * sw;
-        const int y = clampi(oy0 - n + r, 0, a.h - 1), x = clampi(ox0 - n + c, 0, a.w - 1);
-        s[r][c] = ldd(src, (size_t)y * a.src_pitch + x) - (double)a.dc;
+    const int ox0 = blockIdx.x * PE_TW, oy0 = blockIdx.y * PE_TH2;
+    // one job per thread: 4 SW jobs <= 512 threads for N <= 3
+    static_assert(JOBS <= PE_THREADS, "one vertical job per thread");
+    const int j = min((int)threadIdx.x, JOBS - 1);
+    const int cj = j % SW, qr = j / SW;
+    double f[IN];
+    {
+        const int x = clampi(ox0 - N + cj, 0, a.w - 1);
+#pragma unroll
+        for (int i = 0; i < IN; ++i) {
+            const int y = clampi(oy0 - N + ROWS * qr + i, 0, a.h - 1);
+            f[i] = ldd(src, (size_t)y * a.src_pitch + x) - (double)a.dc;
+        }
+    }
+    // kv0, kv2 even, kv1 odd
+    if ((int)threadIdx.x < JOBS) {
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            double sm[N + 1], df[N + 1];
+            sym_sums<N>(&f[r], sm, df);
+            vr[0][ROWS * qr + r][cj] = even_tap<N>(a.kv0, f[r + N], sm);
+            vr[1][ROWS * qr + r][cj] = odd_tap<N>(a.kv1, df);
+            vr[2][ROWS * qr + r][cj] = even_tap<N>(a.kv2, f[r + N], sm);
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < PE_TH * sw; i += 256) {
-        const int r = i / sw, c = i - r * sw;
-        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-        for (int t = 0; t <= 2 * n; ++t) {
-            const double f = s[r + t][c];
-            v0 += a.kv0[t] * f;
-            v1 += a.kv1[t] * f;
-            v2 += a.kv2[t] * f;
-        }
-        vr[0][r][c] = v0;
-        vr[1][r][c] = v1;
-        vr[2][r][c] = v2;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < PE_TH * PE_TW; i += 256) {
-        const int r = i / PE_TW, c = i - r * PE_TW;
-        const int y = oy0 + r, x = ox0 + c;
-        if (y > a.h || (y == a.h && !a.packed)) continue;
-        if (x >= a.w || y == a.h) {
-            // packed planes: zero the row padding and the extra row below the
-            // frame (the iteration kernel's bilinear corners may read them
-            // with zero weight)
-            if (a.packed && x < a.dpitch) {
-                const float z[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-                Packed<TOut>::store(a.dst[blockIdx.z], a.dst1[blockIdx.z], (size_t)y * a.dpitch + x, z);
-            }
-            continue;
-        }
-        double bx = 0.0, by = 0.0, axy = 0.0, axx = 0.0, ayy = 0.0;
-        for (int t = 0; t <= 2 * n; ++t) {
-            const double v0 = vr[0][r][c + t], v1 = vr[1][r][c + t], v2 = vr[2][r][c + t];
-            bx += a.hx[t] * v0;
-            axx += a.hxx[t] * v0;
-            by += a.hy[t] * v1;
-            axy += a.hxy[t] * v1;
-            ayy += a.hyy[t] * v2;
-        }
-        float o[5] = {(float)bx, (float)by, (float)axx, (float)ayy, (float)axy};
-        const size_t q = (size_t)y * a.dpitch + x;
+    // horizontal pass: lane = column, so LDS reads are consecutive doubles
+    // and every store instruction writes whole row segments; thread t takes
+    // rows (t >> 6) + 8 i of column t & 63
+    const int c = threadIdx.x & 63, x = ox0 + c;
+#pragma unroll
+    for (int i = 0; i < PE_TH2 / 8; ++i) {
+        const int r = (threadIdx.x >> 6) + 8 * i, y = oy0 + r;
+        if (y > a.h || (y == a.h && !a.packed)) break;
+        double sm[N + 1], df[N + 1];
+        float o[5];
+        sym_sums<N>(&vr[0][r][c], sm, df);
+        o[0] = (float)odd_tap<N>(a.hx, df);
+        o[2] = (float)even_tap<N>(a.hxx, vr[0][r][c + N], sm);
+        sym_sums<N>(&vr[1][r][c], sm, df);
+        o[1] = (float)even_tap<N>(a.hy, vr[1][r][c + N], sm);
+        o[4] = (float)odd_tap<N>(a.hxy, df);
+        sym_sums<N>(&vr[2][r][c], sm, df);
+        o[3] = (float)even_tap<N>(a.hyy, vr[2][r][c + N], sm);
+        const size_t px = (size_t)y * a.dpitch + x;
         if (a.packed) {
-            Packed<TOut>::store(a.dst[blockIdx.z], a.dst1[blockIdx.z], q, o);
-        } else {
-            if (a.round16)
-                for (int k = 0; k < 5; ++k) o[k] = round16(o[k]);
-            for (int k = 0; k < 5; ++k) st((float *)a.dst[blockIdx.z], q + k * a.dplane, o[k]);
+            if (x >= a.dpitch) continue;
+            if (x >= a.w || y == a.h) {
+                // packed planes: zero the row padding and the extra row below
+                // the frame (the iteration kernel's bilinear corners may read
+                // them with zero weight)
+                const float z[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+                Packed<TOut>::store(a.dst[blockIdx.z], a.dst1[blockIdx.z], px, z);
+            } else {
+                Packed<TOut>::store(a.dst[blockIdx.z], a.dst1[blockIdx.z], px, o);
+            }
+        } else if (x < a.w) {
+            for (int p = 0; p < 5; ++p)
+                st((float *)a.dst[blockIdx.z], px + p * a.dplane, a.round16 ? round16(o[p]) : o[p]);
         }
     }
 }
@@ -417,6 +491,12 @@ struct IterArgs {
     float eps;
     float *m2;               // nullable: epilogue writes |d|^2
     int32_t m2_pitch;
+    // nullable: epilogue writes the pre-mask [|d|^2 > tau^2] (bits t2bits)
+    // as bytes, pitch w, instead of |d|^2 (the absolute threshold is known
+    // before the flow), and block 0 records t2bits in *st
+    uint8_t *pre8;
+    uint32_t t2bits;
+    SelState *st;
 };
 
 __device__ __forceinline__ float bilerp(float p00, float p01, float p10, float p11, float fx, float fy)
@@ -666,6 +746,7 @@ __device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs,
                                     vv[4 * IT_CH * IT_TW], a.eps);
             a.fout[(size_t)oy * a.fout_pitch + x] = d;
             if (a.m2) a.m2[(size_t)oy * a.m2_pitch + x] = mag2(d);
+            if (a.pre8) a.pre8[(size_t)oy * a.w + x] = __float_as_uint(mag2(d)) > a.t2bits ? 1 : 0;
         }
     }
     // no barrier: vs is next written by 3a of a later chunk, two barriers away
@@ -674,6 +755,7 @@ __device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs,
 template <typename TS, int R, int PRIOR>
 __global__ __launch_bounds__(IT_THREADS) void k_iter(IterArgs a, int32_t strip, int32_t nx, int32_t ntiles)
 {
+    if (a.st && blockIdx.x == 0 && threadIdx.x == 0) a.st->tau2_bits = a.t2bits;
     using G = IterGeom<R>;
     __shared__ float lds[G::GH + G::HN + G::VS];
 
@@ -732,7 +814,6 @@ __global__ __launch_bounds__(IT_THREADS) void k_iter(IterArgs a, int32_t strip, 
 // values that share it (0 = the largest), state[2] = tau^2 bits when done.
 constexpr int SEL_BINS = 2048;
 
-struct SelState { uint32_t prefix, rank, tau2_bits, pad; };
 
 // The global histogram is kept in SEL_COPIES copies, block b adding into
 // copy b mod SEL_COPIES, so that a bin's atomics from a thousand blocks
@@ -962,6 +1043,81 @@ __global__ __launch_bounds__(256) void k_dilate(DilArgs a)
 #pragma unroll
         for (int u = -r; u <= r; ++u) m |= dist[rr + r + u][c] <= a.hw[u + r] ? 1 : 0;
         a.mask[(size_t)y * a.mask_pitch + x] = m;
+    }
+}
+
+// Bit-parallel dilation for radii up to DB_MAXR: a 64-column tile row with
+// a halo of r columns on each side is a 128-bit word from two wave ballots
+// (bit k = column ox0 - r + k; pixels outside the frame are 0); the output
+// row y is the OR over row offsets u of the word of row y + u dilated
+// horizontally by the SE's half-width hw(u). Tile: 64 x 32 outputs.
+constexpr int DB_TH = 32, DB_MAXR = 16;
+typedef unsigned __int128 u128d;
+
+template <int MODE> // 0: |d|^2 bits above tau^2 bits; 1: pre-mask bytes; 2: component labels and areas
+__global__ __launch_bounds__(256) void k_dilate_bits(DilArgs a)
+{
+    __shared__ uint64_t rows[DB_TH + 2 * DB_MAXR][2];
+    __shared__ uint64_t out[DB_TH];
+    const int r = a.r, tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int ox0 = blockIdx.x * DIL_TW - r, oy0 = blockIdx.y * DB_TH - r;
+    const int nrows = DB_TH + 2 * r;
+    const uint32_t t2 = MODE == 0 ? a.st->tau2_bits : 0u;
+    // the decision at (y, x), loaded at clamped coordinates (always a valid
+    // address, no branch, so every load of the thread is in flight before
+    // the first ballot) and masked by `in`
+    auto pre_at = [&](int y, int x, bool in) -> bool {
+        const int yc = min(max(y, 0), a.h - 1), xc = min(max(x, 0), a.w - 1);
+        bool v;
+        if (MODE == 0) {
+            v = __float_as_uint(a.m2[(size_t)yc * a.m2_pitch + xc]) > t2;
+        } else if (MODE == 1) {
+            v = a.pre8[(size_t)yc * a.w + xc] != 0;
+        } else {
+            const int32_t l = a.lab[(size_t)yc * a.w + xc];
+            v = l >= 0 && a.area[l] >= a.min_area;
+        }
+        return v && in && y >= 0 && y < a.h && x >= 0 && x < a.w;
+    };
+    // wave ty takes rows ty + 4k, lane tx columns tx and tx + 64 (the latter
+    // only in the right halo); out-of-tile rows are clamped and discarded
+    const int nk = (nrows - ty + 3) / 4;
+    constexpr int LR = (DB_TH + 2 * DB_MAXR) / 4;
+    bool d0[LR], d1[LR];
+#pragma unroll
+    for (int k = 0; k < LR; ++k) {
+        const int ly = ty + 4 * k;
+        d0[k] = pre_at(oy0 + ly, ox0 + tx, k < nk);
+        d1[k] = pre_at(oy0 + ly, ox0 + 64 + tx, k < nk && tx < 2 * r);
+    }
+#pragma unroll
+    for (int k = 0; k < LR; ++k) {
+        const int ly = ty + 4 * k;
+        const uint64_t lo = __ballot(d0[k]), hi = __ballot(d1[k]);
+        if (k < nk && tx == 0) {
+            rows[ly][0] = lo;
+            rows[ly][1] = hi;
+        }
+    }
+    __syncthreads();
+    if (ty == 0 && tx < DB_TH) {
+        u128d m = 0;
+        for (int u = -r; u <= r; ++u) {
+            const int ly = tx + r + u;
+            const u128d x = ((u128d)rows[ly][1] << 64) | rows[ly][0];
+            u128d e = x;
+            for (int q = 1; q <= a.hw[u + r]; ++q) e |= (x << q) | (x >> q);
+            m |= e;
+        }
+        out[tx] = (uint64_t)(m >> r); // the tile's own 64 columns
+    }
+    __syncthreads();
+    const int x = blockIdx.x * DIL_TW + tx;
+    if (x >= a.w) return;
+    for (int yy = ty; yy < DB_TH; yy += 4) {
+        const int y = blockIdx.y * DB_TH + yy;
+        if (y >= a.h) break;
+        a.mask[(size_t)y * a.mask_pitch + x] = (uint8_t)((out[yy] >> tx) & 1);
     }
 }
 
@@ -1475,18 +1631,18 @@ struct PhaseState { int32_t sy, sx; float peak; uint32_t valid; };
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 
-// twiddles tw[m] = exp(-2 pi i m / P) (m < P/2) and the Hann window
+// twiddles tw[m] = exp(-2 pi i m / P) (m < P) and the Hann window
 // hann[i] = (1 - cos(2 pi i / (P - 1))) / 2, in double, rounded to float;
-// clears the argmax counters. grid: ceil((P/2 + P)/256) blocks, 256 threads
+// clears the argmax counters. grid: ceil(2P/256) blocks, 256 threads
 __global__ __launch_bounds__(256) void k_ph_tables(float2 *tw, float *hann, unsigned long long *keys, int32_t P)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < P / 2) {
+    if (i < P) {
         double sn, cs;
         sincospi(-2.0 * (double)i / (double)P, &sn, &cs);
         tw[i] = make_float2((float)cs, (float)sn);
-    } else if (i < P / 2 + P) {
-        const int j = i - P / 2;
+    } else if (i < 2 * P) {
+        const int j = i - P;
         hann[j] = (float)(0.5 - 0.5 * cospi(2.0 * (double)j / (double)(P - 1)));
     }
     if (blockIdx.x == 0 && threadIdx.x < PH_SLOTS) keys[threadIdx.x * PH_SLOT_STRIDE] = 0ull;
@@ -1518,45 +1674,128 @@ __global__ __launch_bounds__(256) void k_ph_pack(PhArgs g)
     g.z[(size_t)y * g.P + x] = make_float2(wgt * g.a[q], wgt * g.b[q]);
 }
 
-// One radix-2 Stockham FFT per row of a P x P complex field, in LDS (two
-// P-point buffers; natural order in and out). INV: inverse with 1/P. LAST
-// (inverse only): instead of storing the row, the real parts go to `surface`
-// (nullable) and into the argmax keys. grid: P blocks, 256 threads, 2 P
-// float2 of dynamic LDS
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// v * (-i) forward, v * (+i) inverse
+template <bool INV> __device__ __forceinline__ float2 mul_mi(float2 v)
+{
+    return INV ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+}
+
+// In-register DFT of R = 2, 4, 8 points, natural order in and out:
+// X(k) = sum_r v(r) exp(-+2 pi i r k / R).
+template <bool INV, int R> __device__ __forceinline__ void dft_small(float2 *v);
+
+template <> __device__ __forceinline__ void dft_small<false, 2>(float2 *v)
+{
+    const float2 a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+}
+template <> __device__ __forceinline__ void dft_small<true, 2>(float2 *v) { dft_small<false, 2>(v); }
+
+template <bool INV> __device__ __forceinline__ void dft4(float2 *v)
+{
+    const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]), t2 = cadd(v[1], v[3]), t3 = mul_mi<INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+}
+template <> __device__ __forceinline__ void dft_small<false, 4>(float2 *v) { dft4<false>(v); }
+template <> __device__ __forceinline__ void dft_small<true, 4>(float2 *v) { dft4<true>(v); }
+
+template <bool INV> __device__ __forceinline__ void dft8(float2 *v)
+{
+    float2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<INV>(e);
+    dft4<INV>(o);
+    constexpr float c = 0.70710678118654752f;
+    // o(k) * exp(-+2 pi i k / 8)
+    const float2 o1 = INV ? make_float2(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y))
+                          : make_float2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
+    const float2 o2 = mul_mi<INV>(o[2]);
+    const float2 o3 = INV ? make_float2(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y))
+                          : make_float2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+}
+template <> __device__ __forceinline__ void dft_small<false, 8>(float2 *v) { dft8<false>(v); }
+template <> __device__ __forceinline__ void dft_small<true, 8>(float2 *v) { dft8<true>(v); }
+
+// One radix-R Stockham step over an N-point sequence (Ns: the size of the
+// sub-transforms already done): job j takes the R values j + r N/R, turns
+// them by exp(-+2 pi i r k / (Ns R)) with k = j mod Ns (table entry
+// r k N / (Ns R) of the full-circle table), transforms them in registers and
+// stores them at (j - k) R + k + r Ns.
+template <bool INV, int R>
+__device__ __forceinline__ void fft_step(const float2 *src, float2 *dst, int N, int Ns, const float2 *tw, float scale)
+{
+    const int stride = N / (Ns * R);
+    for (int j = threadIdx.x; j < N / R; j += 256) {
+        const int k = j & (Ns - 1);
+        float2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = src[j + r * (N / R)];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            float2 t = tw[(r * k * stride) & (N - 1)];
+            if (INV) t.y = -t.y;
+            v[r] = cmul(v[r], t);
+        }
+        dft_small<INV, R>(v);
+        const int d = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[d + r * Ns] = make_float2(v[r].x * scale, v[r].y * scale);
+    }
+}
+
+// One Stockham FFT per row of a P x P complex field (P a power of two):
+// radix-8 steps then one radix-4 or radix-2 step, each step a pass through
+// LDS (two P-point buffers), the first reading the row from global memory
+// and the last writing it back. INV: inverse with 1/P. LAST (inverse only):
+// instead of storing the row, the real parts go to `surface` (nullable) and
+// into the argmax keys. grid: P blocks, 256 threads, 2 P float2 of dynamic LDS
 template <bool INV, bool LAST>
 __global__ __launch_bounds__(256) void k_fft_rows(float2 *data, int32_t P, const float2 *tw, float *surface,
                                                   unsigned long long *keys)
 {
     extern __shared__ float2 fsm[];
-    float2 *src = fsm, *dst = fsm + P;
     float2 *row = data + (size_t)blockIdx.x * P;
-    for (int i = threadIdx.x; i < P; i += 256) src[i] = row[i];
-    __syncthreads();
-    const int half = P >> 1;
-    for (int Ns = 1; Ns < P; Ns <<= 1) {
-        const int step = half / Ns; // twiddle index stride: exp(-2 pi i k / (2 Ns)) = tw[k P / (2 Ns)]
-        for (int j = threadIdx.x; j < half; j += 256) {
-            const int k = j & (Ns - 1);
-            float2 t = tw[k * step];
-            if (INV) t.y = -t.y;
-            const float2 v0 = src[j], v1 = cmul(src[j + half], t);
-            const int d = ((j - k) << 1) + k;
-            dst[d] = make_float2(v0.x + v1.x, v0.y + v1.y);
-            dst[d + Ns] = make_float2(v0.x - v1.x, v0.y - v1.y);
+    const int lg = __ffs(P) - 1, n8 = lg / 3, rem = lg % 3;
+    const int steps = n8 + (rem ? 1 : 0);
+    const float sc = INV ? 1.0f / (float)P : 1.0f;
+    const float2 *src = row;
+    int Ns = 1;
+    for (int st = 0; st < steps; ++st) {
+        const bool last = st == steps - 1;
+        float2 *dst = fsm + (st & 1) * P;
+        if (last && !LAST) dst = row;
+        const float scale = last ? sc : 1.0f;
+        if (st < n8) {
+            fft_step<INV, 8>(src, dst, P, Ns, tw, scale);
+            Ns *= 8;
+        } else if (rem == 2) {
+            fft_step<INV, 4>(src, dst, P, Ns, tw, scale);
+            Ns *= 4;
+        } else {
+            fft_step<INV, 2>(src, dst, P, Ns, tw, scale);
+            Ns *= 2;
         }
         __syncthreads();
-        float2 *tmp = src;
         src = dst;
-        dst = tmp;
     }
-    const float sc = INV ? 1.0f / (float)P : 1.0f;
-    if (!LAST) {
-        for (int i = threadIdx.x; i < P; i += 256) row[i] = make_float2(src[i].x * sc, src[i].y * sc);
-        return;
-    }
+    if (!LAST) return;
     unsigned long long best = 0ull;
     for (int i = threadIdx.x; i < P; i += 256) {
-        const float v = src[i].x * sc;
+        const float v = src[i].x;
         if (surface) surface[(size_t)blockIdx.x * P + i] = v;
         const uint32_t b = __float_as_uint(v);
         const uint32_t ord = (b & 0x80000000u) ? ~b : (b | 0x80000000u); // orders like the float

@@ -429,8 +429,10 @@ def push_many(streams, frames, flows, masks, stream=None):
     return list(st)
 
 
-def timing_enable(on=True):
-    lib().roi_timing_enable(1 if on else 0)
+def timing_enable(on=True, per_call=False):
+    """Iteration-kernel timing: off, per launch, or (per_call) one bracket
+    around each call's run of iteration launches."""
+    lib().roi_timing_enable((2 if per_call else 1) if on else 0)
 
 
 def timing_reset():

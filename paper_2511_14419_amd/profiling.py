@@ -41,8 +41,10 @@ def _dispatches(run_dir):
     return [out[k] for k in sorted(out)]
 
 
-def _iter_algorithmic(levels, n, ts):
-    """Algorithmic bytes of the iteration launches of one pair, in launch order."""
+def _iter_algorithmic(levels, n, ts, mask_bytes=1):
+    """Algorithmic bytes of the iteration launches of one pair, in launch order.
+    The last launch also writes the mask stage's input: 1 B/px (the pre-mask
+    of an absolute threshold, the plain path's default) or 4 B/px (|d|^2)."""
     out = []
     for l in range(levels - 1, -1, -1):
         px = (n >> l) ** 2
@@ -53,7 +55,7 @@ def _iter_algorithmic(levels, n, ts):
             elif l < levels - 1:
                 b += (px // 4) * 8
             if l == 0 and it == 2:
-                b += px * 4
+                b += px * mask_bytes
             out.append((l, b))
     return out
 
