@@ -325,43 +325,65 @@ struct PhaseBufs {
     unsigned long long *keys;
 };
 
-template <typename TIn>
-void launch_to_float(const void *src, int64_t spitch, float *dst, int dpitch, int h, int w, hipStream_t s)
+
+// One registration: `mov` (element type dmov, row pitch pmov) against `ref`
+// (dref, pref); `out` (floats, row pitch opitch) receives mov moved back by
+// the translation; `copy` (nullable; dcopy, pcopy) is written unmoved as
+// floats into `copy_out` (row pitch opitch).
+struct PhaseIO {
+    const void *ref; roi_dtype dref; int64_t pref;
+    const void *mov; roi_dtype dmov; int64_t pmov;
+    float *out; int opitch;
+    const void *copy; roi_dtype dcopy; int64_t pcopy;
+    float *copy_out;
+};
+
+template <typename TA, typename TB>
+void launch_pack2(const PhArgs &g, dim3 ge, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_to_float<TIn>, dim3((w + 63) / 64, (h + 3) / 4), dim3(256), 0, s, (const TIn *)src, spitch,
-                       dst, dpitch, h, w);
+    hipLaunchKernelGGL((k_ph_pack<TA, TB>), ge, dim3(256), 0, s, g);
 }
 
-void to_float(roi_dtype dt, const void *src, int64_t spitch, float *dst, int dpitch, int h, int w, hipStream_t s)
+template <typename TA>
+void launch_pack(roi_dtype db, const PhArgs &g, dim3 ge, hipStream_t s)
 {
-    if (dt == ROI_U8) launch_to_float<uint8_t>(src, spitch, dst, dpitch, h, w, s);
-    else if (dt == ROI_U16) launch_to_float<uint16_t>(src, spitch, dst, dpitch, h, w, s);
-    else launch_to_float<float>(src, spitch, dst, dpitch, h, w, s);
+    if (db == ROI_U8) launch_pack2<TA, uint8_t>(g, ge, s);
+    else if (db == ROI_U16) launch_pack2<TA, uint16_t>(g, ge, s);
+    else launch_pack2<TA, float>(g, ge, s);
 }
 
-// Registration of `mov` to `ref` (both h x w floats, row pitch `pitch`):
-// the translation by phase correlation over the centred P x P window, then
-// out(y, x) = mov(y + sy, x + sx) with clamped coordinates (row pitch
-// `opitch`); the shift goes to *ph. `surface` (nullable, P x P floats)
+template <typename TS>
+void launch_apply2(roi_dtype d2, const ApplyArgs &a, dim3 g, hipStream_t s)
+{
+    if (d2 == ROI_U8) hipLaunchKernelGGL((k_ph_apply<TS, uint8_t>), g, dim3(256), 0, s, a);
+    else if (d2 == ROI_U16) hipLaunchKernelGGL((k_ph_apply<TS, uint16_t>), g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_ph_apply<TS, float>), g, dim3(256), 0, s, a);
+}
+
+// Registration by phase correlation over the centred P x P window (see
+// PhaseIO); the shift goes to *ph; `surface` (nullable, P x P floats)
 // receives the correlation surface.
-roi_status enqueue_phase(const PhaseBufs &b, const float *ref, const float *mov, int pitch, int h, int w, float *out,
-                         int opitch, PhaseState *ph, float *surface, hipStream_t s)
+roi_status enqueue_phase(const PhaseBufs &b, const PhaseIO &io, int h, int w, PhaseState *ph, float *surface,
+                         hipStream_t s)
 {
     const int P = b.P;
     if (P > 0) {
         hipLaunchKernelGGL(k_ph_tables, dim3((2 * P + 255) / 256), dim3(256), 0, s, b.tw, b.hann, b.keys, P);
         PhArgs g{};
-        g.a = ref;
-        g.b = mov;
-        g.pitch = pitch;
+        g.a = io.ref;
+        g.b = io.mov;
+        g.pitch_a = io.pref;
+        g.pitch_b = io.pmov;
         g.y0 = (h - P) / 2;
         g.x0 = (w - P) / 2;
         g.P = P;
         g.hann = b.hann;
         g.z = b.z;
         const dim3 ge((P + 63) / 64, (P + 3) / 4), gt((P + 31) / 32, (P + 31) / 32);
-        const size_t lds = 2 * (size_t)P * sizeof(float2);
-        hipLaunchKernelGGL(k_ph_pack, ge, dim3(256), 0, s, g);
+        const size_t lds = (2 * (size_t)(P + P / 16) + P) * sizeof(float2); // two padded row buffers + twiddles
+        if (io.dref == ROI_U8) launch_pack<uint8_t>(io.dmov, g, ge, s);
+        else if (io.dref == ROI_U16) launch_pack<uint16_t>(io.dmov, g, ge, s);
+        else launch_pack<float>(io.dmov, g, ge, s);
         hipLaunchKernelGGL((k_fft_rows<false, false>), dim3(P), dim3(256), lds, s, b.z, P, (const float2 *)b.tw,
                            (float *)nullptr, (unsigned long long *)nullptr);
         hipLaunchKernelGGL(k_transpose, gt, dim3(256), 0, s, (const float2 *)b.z, b.t, P);
@@ -374,8 +396,24 @@ roi_status enqueue_phase(const PhaseBufs &b, const float *ref, const float *mov,
         hipLaunchKernelGGL((k_fft_rows<true, true>), dim3(P), dim3(256), lds, s, b.t, P, (const float2 *)b.tw, surface,
                            b.keys);
     }
-    hipLaunchKernelGGL(k_ph_apply, dim3((w + 63) / 64, (h + 3) / 4), dim3(256), 0, s, mov, out, pitch, opitch, h, w,
-                       (const unsigned long long *)b.keys, P, ph);
+    ApplyArgs a{};
+    a.src = io.mov;
+    a.pitch = io.pmov;
+    a.dst = io.out;
+    a.dpitch = io.opitch;
+    a.src2 = io.copy;
+    a.pitch2 = io.pcopy;
+    a.dst2 = io.copy_out;
+    a.h = h;
+    a.w = w;
+    a.P = P;
+    a.keys = b.keys;
+    a.st = ph;
+    const roi_dtype d2 = io.copy ? io.dcopy : ROI_F32;
+    const dim3 g((w + 255) / 256, (h + 3) / 4);
+    if (io.dmov == ROI_U8) launch_apply2<uint8_t>(d2, a, g, s);
+    else if (io.dmov == ROI_U16) launch_apply2<uint16_t>(d2, a, g, s);
+    else launch_apply2<float>(d2, a, g, s);
     LAUNCH_CHECK();
     return ROI_OK;
 }
@@ -425,24 +463,40 @@ roi_status enqueue_expand(const Plan &pl, uint8_t *base, int nf, const void *con
         pitch0 = pl.lv[0].pitch;
     }
     if (p->flags & ROI_STABILIZE) {
+        // the frames as they stand here (raw, or denoised floats); the
+        // registered frame and, for a pair, the first frame as floats are
+        // written by the alignment kernel, so both level-0 inputs are floats
         const int h = pl.lv[0].h, w = pl.lv[0].w, fp = pl.lv[0].pitch;
-        if (!p->denoise) {
-            for (int f = 0; f < nf; ++f) {
-                to_float(dt, frames[f], pitch, (float *)(base + pl.den[set[f]]), fp, h, w, s);
-                lvl0[f] = base + pl.den[set[f]];
-            }
-            dt0 = ROI_F32;
-            pitch0 = fp;
-        }
         const int fn = set[nf - 1];
-        const float *ref = nf == 2 ? (const float *)(base + pl.den[set[0]])
-                                   : (reg_set >= 0 ? (const float *)(base + pl.al[reg_set]) : nullptr);
+        PhaseIO io{};
+        io.mov = lvl0[nf - 1];
+        io.dmov = dt0;
+        io.pmov = pitch0;
+        if (nf == 2) {
+            io.ref = lvl0[0];
+            io.dref = dt0;
+            io.pref = pitch0;
+            if (!p->denoise) {
+                io.copy = lvl0[0];
+                io.dcopy = dt0;
+                io.pcopy = pitch0;
+                io.copy_out = (float *)(base + pl.den[set[0]]);
+            }
+        } else if (reg_set >= 0) {
+            io.ref = base + pl.al[reg_set];
+            io.dref = ROI_F32;
+            io.pref = fp;
+        }
+        io.out = (float *)(base + pl.al[fn]);
+        io.opitch = fp;
         PhaseBufs b = phase_bufs(pl, base);
-        if (!ref) b.P = 0; // first frame of a stream: kept as it is
-        float *out = (float *)(base + pl.al[fn]);
-        roi_status st = enqueue_phase(b, ref, (const float *)(base + pl.den[fn]), fp, h, w, out, fp, ph, nullptr, s);
+        if (!io.ref) b.P = 0; // first frame of a stream: kept as it is
+        roi_status st = enqueue_phase(b, io, h, w, ph, nullptr, s);
         if (st != ROI_OK) return st;
-        lvl0[nf - 1] = out;
+        if (nf == 2 && !p->denoise) lvl0[0] = base + pl.den[set[0]];
+        lvl0[nf - 1] = io.out;
+        dt0 = ROI_F32;
+        pitch0 = fp;
     }
     const float dc0 = dc_of(dt); // the frame's DC constant, also for denoised frames
     for (int l = 1; l < pl.L; ++l) {
@@ -751,9 +805,12 @@ roi_status enqueue_mask(const MaskBufs &mb, SelState *slot, int h, int w, const 
         if (cc) {
             hipLaunchKernelGGL(k_cc_border, gt, dim3(128), 0, s, (const int32_t *)mb.lab, m.link, h, w);
             hipLaunchKernelGGL(k_cc_compress, gt, dim3(256), 0, s, mb.lab, m.link, mb.area, h, w);
-            d.lab = mb.lab;
-            d.area = mb.area;
-            d.min_area = p->min_area;
+            // the kept components as pre-mask bytes (into the saliency plane,
+            // no longer read), so the dilation reads one byte per pixel
+            const int64_t n = (int64_t)h * w;
+            hipLaunchKernelGGL(k_cc_keep, dim3((unsigned)((n + 1023) / 1024)), dim3(256), 0, s,
+                               (const int32_t *)mb.lab, (const int32_t *)mb.area, p->min_area, n, (uint8_t *)mb.sal);
+            d.pre8 = (const uint8_t *)mb.sal;
         } else {
             d.pre8 = (const uint8_t *)mb.lab;
         }
@@ -1073,12 +1130,12 @@ roi_status roi_read_shift(const void *ws, int32_t index, int32_t *sy, int32_t *s
 
 int32_t roi_phase_size(int32_t h, int32_t w) { return h < 0 || w < 0 ? 0 : phase_size(h, w); }
 
-// Workspace of roi_phase_correlation after the header: both frames as
-// floats and the registered frame (h rows of a 64-aligned pitch each), the
-// two complex fields, the tables and the argmax counters.
+// Workspace of roi_phase_correlation after the header: the registered frame
+// (h rows of a 64-aligned pitch), the two complex fields, the tables and the
+// argmax counters.
 struct PhasePlan {
     int pitch;
-    size_t f[2], al, z, t, tw, hann, keys, bytes;
+    size_t al, z, t, tw, hann, keys, bytes;
 };
 
 PhasePlan phase_plan(int h, int w)
@@ -1091,10 +1148,7 @@ PhasePlan phase_plan(int h, int w)
         off = align_up(off + b, ALIGN);
         return o;
     };
-    const size_t plane = (size_t)h * q.pitch * sizeof(float);
-    q.f[0] = take(plane);
-    q.f[1] = take(plane);
-    q.al = take(plane);
+    q.al = take((size_t)h * q.pitch * sizeof(float));
     const size_t P = (size_t)phase_size(h, w);
     q.z = take(P * P * sizeof(float2));
     q.t = take(P * P * sizeof(float2));
@@ -1125,9 +1179,6 @@ roi_status roi_phase_correlation(const void *prev, const void *next, int32_t h, 
     if (ws_bytes < HDR_BYTES + q.bytes) return ROI_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
     uint8_t *base = (uint8_t *)ws + HDR_BYTES;
-    float *f0 = (float *)(base + q.f[0]), *f1 = (float *)(base + q.f[1]);
-    to_float(dtype, prev, pitch, f0, q.pitch, h, w, s);
-    to_float(dtype, next, pitch, f1, q.pitch, h, w, s);
     PhaseBufs b{};
     b.P = phase_size(h, w);
     b.z = (float2 *)(base + q.z);
@@ -1135,9 +1186,16 @@ roi_status roi_phase_correlation(const void *prev, const void *next, int32_t h, 
     b.tw = (float2 *)(base + q.tw);
     b.hann = (float *)(base + q.hann);
     b.keys = (unsigned long long *)(base + q.keys);
-    float *out = aligned ? aligned : (float *)(base + q.al);
-    return enqueue_phase(b, f0, f1, q.pitch, h, w, out, aligned ? w : q.pitch, phase_slot(ws, 0),
-                         b.P > 0 ? surface : nullptr, s);
+    PhaseIO io{};
+    io.ref = prev;
+    io.dref = dtype;
+    io.pref = pitch;
+    io.mov = next;
+    io.dmov = dtype;
+    io.pmov = pitch;
+    io.out = aligned ? aligned : (float *)(base + q.al);
+    io.opitch = aligned ? w : q.pitch;
+    return enqueue_phase(b, io, h, w, phase_slot(ws, 0), b.P > 0 ? surface : nullptr, s);
 }
 
 // Workspace of roi_mask_from_flow after the header: m2 and sal (h rows of a

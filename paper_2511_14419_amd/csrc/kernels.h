@@ -1648,30 +1648,24 @@ __global__ __launch_bounds__(256) void k_ph_tables(float2 *tw, float *hann, unsi
     if (blockIdx.x == 0 && threadIdx.x < PH_SLOTS) keys[threadIdx.x * PH_SLOT_STRIDE] = 0ull;
 }
 
-// level-0 frame of any input type as floats. grid: (ceil(w/64), ceil(h/4))
-template <typename TIn>
-__global__ __launch_bounds__(256) void k_to_float(const TIn *src, int64_t spitch, float *dst, int32_t dpitch,
-                                                  int32_t h, int32_t w)
-{
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (x < w && y < h) dst[(size_t)y * dpitch + x] = (float)src[(size_t)y * spitch + x];
-}
-
 struct PhArgs {
-    const float *a, *b; int32_t pitch; // the two float frames
-    int32_t y0, x0, P;                 // the window
+    const void *a, *b; int64_t pitch_a, pitch_b; // the two frames (reference, moving)
+    int32_t y0, x0, P;                           // the window
     const float *hann;
-    float2 *z;                         // P x P
+    float2 *z;                                   // P x P
 };
 
-// z = hann(y) hann(x) (a + i b) over the window. grid: (P/64, P/4)
+// z = hann(y) hann(x) (a + i b) over the window, frames read in their own
+// element types. grid: (ceil(P/64), ceil(P/4))
+template <typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_ph_pack(PhArgs g)
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= g.P || y >= g.P) return;
-    const size_t q = (size_t)(g.y0 + y) * g.pitch + g.x0 + x;
+    const float va = (float)((const TA *)g.a)[(size_t)(g.y0 + y) * g.pitch_a + g.x0 + x];
+    const float vb = (float)((const TB *)g.b)[(size_t)(g.y0 + y) * g.pitch_b + g.x0 + x];
     const float wgt = g.hann[y] * g.hann[x];
-    g.z[(size_t)y * g.P + x] = make_float2(wgt * g.a[q], wgt * g.b[q]);
+    g.z[(size_t)y * g.P + x] = make_float2(wgt * va, wgt * vb);
 }
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -1735,15 +1729,23 @@ template <> __device__ __forceinline__ void dft_small<true, 8>(float2 *v) { dft8
 // them by exp(-+2 pi i r k / (Ns R)) with k = j mod Ns (table entry
 // r k N / (Ns R) of the full-circle table), transforms them in registers and
 // stores them at (j - k) R + k + r Ns.
+// LDS buffers are indexed with one float2 of padding after every 16, so
+// the strided stores of the first steps spread over the banks
+__device__ __forceinline__ int fpad(int i) { return i + (i >> 4); }
+
 template <bool INV, int R>
-__device__ __forceinline__ void fft_step(const float2 *src, float2 *dst, int N, int Ns, const float2 *tw, float scale)
+__device__ __forceinline__ void fft_step(const float2 *src, bool src_lds, float2 *dst, bool dst_lds, int N, int Ns,
+                                         const float2 *tw, float scale)
 {
     const int stride = N / (Ns * R);
     for (int j = threadIdx.x; j < N / R; j += 256) {
         const int k = j & (Ns - 1);
         float2 v[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = src[j + r * (N / R)];
+        for (int r = 0; r < R; ++r) {
+            const int i = j + r * (N / R);
+            v[r] = src[src_lds ? fpad(i) : i];
+        }
 #pragma unroll
         for (int r = 1; r < R; ++r) {
             float2 t = tw[(r * k * stride) & (N - 1)];
@@ -1753,7 +1755,10 @@ __device__ __forceinline__ void fft_step(const float2 *src, float2 *dst, int N, 
         dft_small<INV, R>(v);
         const int d = (j - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) dst[d + r * Ns] = make_float2(v[r].x * scale, v[r].y * scale);
+        for (int r = 0; r < R; ++r) {
+            const int i = d + r * Ns;
+            dst[dst_lds ? fpad(i) : i] = make_float2(v[r].x * scale, v[r].y * scale);
+        }
     }
 }
 
@@ -1762,7 +1767,8 @@ __device__ __forceinline__ void fft_step(const float2 *src, float2 *dst, int N, 
 // LDS (two P-point buffers), the first reading the row from global memory
 // and the last writing it back. INV: inverse with 1/P. LAST (inverse only):
 // instead of storing the row, the real parts go to `surface` (nullable) and
-// into the argmax keys. grid: P blocks, 256 threads, 2 P float2 of dynamic LDS
+// into the argmax keys. grid: P blocks, 256 threads, 2 fpad(P) + P float2
+// of dynamic LDS (two row buffers and the twiddle table)
 template <bool INV, bool LAST>
 __global__ __launch_bounds__(256) void k_fft_rows(float2 *data, int32_t P, const float2 *tw, float *surface,
                                                   unsigned long long *keys)
@@ -1772,30 +1778,42 @@ __global__ __launch_bounds__(256) void k_fft_rows(float2 *data, int32_t P, const
     const int lg = __ffs(P) - 1, n8 = lg / 3, rem = lg % 3;
     const int steps = n8 + (rem ? 1 : 0);
     const float sc = INV ? 1.0f / (float)P : 1.0f;
+    const int buf = fpad(P); // padded buffer length
+    // the twiddle table staged once per block after the two row buffers
+    float2 *tws = fsm + 2 * buf;
+    for (int i = threadIdx.x; i < P; i += 256) tws[i] = tw[i];
+    __syncthreads();
+    tw = tws;
     const float2 *src = row;
+    bool src_lds = false;
     int Ns = 1;
     for (int st = 0; st < steps; ++st) {
         const bool last = st == steps - 1;
-        float2 *dst = fsm + (st & 1) * P;
-        if (last && !LAST) dst = row;
+        float2 *dst = fsm + (st & 1) * buf;
+        bool dst_lds = true;
+        if (last && !LAST) {
+            dst = row;
+            dst_lds = false;
+        }
         const float scale = last ? sc : 1.0f;
         if (st < n8) {
-            fft_step<INV, 8>(src, dst, P, Ns, tw, scale);
+            fft_step<INV, 8>(src, src_lds, dst, dst_lds, P, Ns, tw, scale);
             Ns *= 8;
         } else if (rem == 2) {
-            fft_step<INV, 4>(src, dst, P, Ns, tw, scale);
+            fft_step<INV, 4>(src, src_lds, dst, dst_lds, P, Ns, tw, scale);
             Ns *= 4;
         } else {
-            fft_step<INV, 2>(src, dst, P, Ns, tw, scale);
+            fft_step<INV, 2>(src, src_lds, dst, dst_lds, P, Ns, tw, scale);
             Ns *= 2;
         }
         __syncthreads();
         src = dst;
+        src_lds = dst_lds;
     }
     if (!LAST) return;
     unsigned long long best = 0ull;
     for (int i = threadIdx.x; i < P; i += 256) {
-        const float v = src[i].x;
+        const float v = src[src_lds ? fpad(i) : i].x;
         if (surface) surface[(size_t)blockIdx.x * P + i] = v;
         const uint32_t b = __float_as_uint(v);
         const uint32_t ord = (b & 0x80000000u) ? ~b : (b | 0x80000000u); // orders like the float
@@ -1850,14 +1868,27 @@ __global__ __launch_bounds__(256) void k_ph_cross(const float2 *zt, float2 *rt, 
     rt[(size_t)kx * P + ky] = r;
 }
 
+struct ApplyArgs {
+    const void *src; int64_t pitch;    // the frame to move (its own element type)
+    float *dst; int32_t dpitch;        // the registered frame, as floats
+    const void *src2; int64_t pitch2;  // nullable: a frame copied unmoved, as floats,
+    float *dst2;                       //   into dst2 (row pitch dpitch)
+    int32_t h, w, P;
+    const unsigned long long *keys;
+    PhaseState *st;                    // nullable
+};
+
 // The shift from the argmax keys (every block decodes it), then
 // dst(y, x) = src(y + sy, x + sx), coordinates clamped into the frame; block
-// (0, 0) records the shift (st nullable). P == 0: no estimate, zero shift.
-// grid: (ceil(w/64), ceil(h/4)), 256 threads
-__global__ __launch_bounds__(256) void k_ph_apply(const float *src, float *dst, int32_t pitch, int32_t dpitch,
-                                                  int32_t h, int32_t w, const unsigned long long *keys, int32_t P,
-                                                  PhaseState *st)
+// (0, 0) records the shift. P == 0: no estimate, zero shift. A thread
+// writes 4 consecutive pixels of a row.
+// grid: (ceil(w/256), ceil(h/4)), 256 threads
+template <typename TS, typename TS2>
+__global__ __launch_bounds__(256) void k_ph_apply(ApplyArgs a)
 {
+    const unsigned long long *keys = a.keys;
+    const int P = a.P, h = a.h, w = a.w;
+    PhaseState *st = a.st;
     int sy = 0, sx = 0;
     float peak = 0.0f;
     if (P > 0) {
@@ -1873,15 +1904,48 @@ __global__ __launch_bounds__(256) void k_ph_apply(const float *src, float *dst, 
         sy = py >= P / 2 ? py - P : py;
         sx = px >= P / 2 ? px - P : px;
     }
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (st && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         st->sy = sy;
         st->sx = sx;
         st->peak = peak;
         st->valid = 1;
     }
-    if (x < w && y < h)
-        dst[(size_t)y * dpitch + x] = src[(size_t)min(max(y + sy, 0), h - 1) * pitch + min(max(x + sx, 0), w - 1)];
+    if (y >= h) return;
+    const TS *src = (const TS *)a.src + (size_t)min(max(y + sy, 0), h - 1) * a.pitch;
+    const TS2 *src2 = a.src2 ? (const TS2 *)a.src2 + (size_t)y * a.pitch2 : nullptr;
+    const int x0 = blockIdx.x * 256 + (threadIdx.x & 63) * 4;
+    float v[4], c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int xk = min(x0 + k, w - 1);
+        v[k] = (float)src[min(max(xk + sx, 0), w - 1)];
+        c[k] = src2 ? (float)src2[xk] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (x0 + k >= w) break;
+        a.dst[(size_t)y * a.dpitch + x0 + k] = v[k];
+        if (a.src2) a.dst2[(size_t)y * a.dpitch + x0 + k] = c[k];
+    }
+}
+
+// Pre-mask bytes of the kept components: [lab(p) >= 0 and area(lab(p)) >=
+// min_area], 4 pixels per thread with all loads in flight.
+// grid: ceil(h w / 1024) blocks, 256 threads
+__global__ __launch_bounds__(256) void k_cc_keep(const int32_t *lab, const int32_t *area, int32_t min_area,
+                                                 int64_t n, uint8_t *pre)
+{
+    const int64_t b = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    int32_t l[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) l[k] = b + k < n ? lab[b + k] : -1;
+    int32_t ar[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ar[k] = l[k] >= 0 ? area[l[k]] : 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (b + k < n) pre[b + k] = l[k] >= 0 && ar[k] >= min_area ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- adjacent-frame ensemble
