@@ -11,6 +11,11 @@ iteration kernel has a known algorithmic byte count.
         python -m paper_2511_14419_amd.profile_run
 
 then ``python -m paper_2511_14419_amd.profiling traffic OUT/fetch OUT/write``.
+
+``--mode`` selects the path: ``plain`` (default parameters), ``saliency``
+(the saliency rule: top 20 % of saliency, 3x3 opening and closing,
+components of at least 32 px), ``stabilize`` (phase-correlation
+stabilisation on) or ``denoise`` (denoising pre-stage on, sigma_range 60).
 """
 import argparse
 
@@ -22,6 +27,7 @@ def main():
     ap.add_argument("--pairs", type=int, default=3)
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--fp16", action="store_true")
+    ap.add_argument("--mode", choices=["plain", "saliency", "stabilize", "denoise"], default="plain")
     args = ap.parse_args()
 
     import torch
@@ -39,14 +45,18 @@ def main():
     seq = synth.sequence_u16(n, n, args.pairs + 1, max(1, 200 * n * n // (2048 * 2048)), 100)
     frames = [torch.from_numpy(s).to(dev) for s in seq]
     fl.autotune(0)
-    p = fl.default_params(flags=fl.ROI_FP16_STORAGE if args.fp16 else 0)
+    kw = {"plain": {}, "saliency": dict(rule=fl.ROI_RULE_SALIENCY, thresh_mode=1, thresh=0.2),
+          "stabilize": dict(flags=fl.ROI_STABILIZE), "denoise": dict(denoise=1, sigma_range=60.0)}[args.mode]
+    if args.fp16:
+        kw["flags"] = kw.get("flags", 0) | fl.ROI_FP16_STORAGE
+    p = fl.default_params(**kw)
     flow = torch.empty((n, n, 2), device=dev)
     mask = torch.empty((n, n), dtype=torch.uint8, device=dev)
     ws = fl.alloc_workspace(fl.workspace_size(n, n, fl.ROI_U16, p), dev)
     for i in range(args.pairs):
         fl.roi_mask(frames[i], frames[i + 1], p, flow=flow, mask=mask, ws=ws)
     torch.cuda.synchronize()
-    print("profile_run: %d pairs %dx%d done" % (args.pairs, n, n), flush=True)
+    print("profile_run: %d pairs %dx%d (%s) done" % (args.pairs, n, n, args.mode), flush=True)
 
 
 if __name__ == "__main__":
