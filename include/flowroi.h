@@ -404,7 +404,10 @@ void roi_autotune(int32_t mode);
 roi_status roi_set_strip(int32_t strip);
 
 /* Tuned strip height for a level of h x w with this window and storage
- * (fp16 != 0: FP16), or 0 if that shape has not been tuned yet. */
+ * (fp16 != 0: FP16), or 0 if that shape has not been tuned yet. Strips are
+ * tuned per prior mode; this returns the one of the launches that start
+ * from the same level's flow, else from the upsampled coarser flow, else
+ * from zero. */
 int32_t roi_tuned_strip(int32_t h, int32_t w, int32_t winsize, int32_t fp16);
 
 const char *roi_status_str(roi_status s);

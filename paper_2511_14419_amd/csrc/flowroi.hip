@@ -549,24 +549,26 @@ roi_status enqueue_expand(const Plan &pl, uint8_t *base, int nf, const void *con
 
 // The strip height of the iteration kernel only changes how work is split
 // (results are bitwise identical for every strip), so it is tuned per
-// (level size, window, storage) by timing the candidates on the real data
+// (level size, window, storage, prior mode) by timing the candidates on the real data
 // the first time a shape is seen (each candidate run rewrites the same
 // output). Captured launches and disabled tuning use the heuristic.
-constexpr int STRIP_CANDIDATES[] = {8, 16, 32, 64, 128, 256};
+constexpr int STRIP_CANDIDATES[] = {8, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+constexpr int N_STRIP_CANDIDATES = sizeof(STRIP_CANDIDATES) / sizeof(STRIP_CANDIDATES[0]);
 
 struct TuneState {
     std::mutex mu;
     int mode = 1;        // 0 heuristic only, 1 tune on first use
     int forced = 0;      // > 0: every launch uses this strip
-    std::map<std::tuple<int, int, int, int>, int> best;
+    std::map<std::tuple<int, int, int, int, int>, int> best;
 } g_tune;
 
 int heuristic_strip(int h, int w)
 {
-    // aim for >= 1024 workgroups (4 per CU) without strips shorter than 16 rows
+    // aim for >= 512 workgroups (2 per CU: measured best on 2048^2 and
+    // 1024^2 levels, where more resident strips thrash the L1 cache)
     const int nx = (w + IT_TW - 1) / IT_TW;
     int strip = 256;
-    while (strip > 16 && (long)nx * ((h + strip - 1) / strip) < 1024) strip /= 2;
+    while (strip > 8 && (long)nx * ((h + strip - 1) / strip) < 512) strip /= 2;
     return strip;
 }
 
@@ -620,26 +622,26 @@ int choose_strip(const IterArgs &a, bool fp16, hipStream_t s)
 {
     std::lock_guard<std::mutex> lk(g_tune.mu);
     if (g_tune.forced > 0) return g_tune.forced;
-    const auto key = std::make_tuple(a.h, a.w, a.R, fp16 ? 1 : 0);
+    const auto key = std::make_tuple(a.h, a.w, a.R, fp16 ? 1 : 0, a.prior);
     auto it = g_tune.best.find(key);
     if (it != g_tune.best.end()) return it->second;
     if (g_tune.mode == 0 || capturing(s)) return heuristic_strip(a.h, a.w);
-    hipEvent_t e[2 * 6];
+    constexpr int NE = 2 * N_STRIP_CANDIDATES;
+    hipEvent_t e[NE];
     int n = 0;
-    for (int k = 0; k < 12; ++k)
-        if (hipEventCreate(&e[k]) == hipSuccess) ++n;
+    while (n < NE && hipEventCreate(&e[n]) == hipSuccess) ++n;
     int best = heuristic_strip(a.h, a.w);
-    if (n == 12) {
+    if (n == NE) {
         float best_ms = 1e30f;
-        for (int c = 0; c < 6; ++c) {
+        for (int c = 0; c < N_STRIP_CANDIDATES; ++c) {
             const int strip = STRIP_CANDIDATES[c];
             launch_iter_raw(a, fp16, strip, s); // warm the caches / code object
             hipEventRecord(e[2 * c], s);
             launch_iter_raw(a, fp16, strip, s);
             hipEventRecord(e[2 * c + 1], s);
         }
-        if (hipEventSynchronize(e[11]) == hipSuccess) {
-            for (int c = 0; c < 6; ++c) {
+        if (hipEventSynchronize(e[NE - 1]) == hipSuccess) {
+            for (int c = 0; c < N_STRIP_CANDIDATES; ++c) {
                 float ms = 0;
                 if (hipEventElapsedTime(&ms, e[2 * c], e[2 * c + 1]) == hipSuccess && ms < best_ms) {
                     best_ms = ms;
@@ -1652,8 +1654,11 @@ roi_status roi_set_strip(int32_t strip)
 int32_t roi_tuned_strip(int32_t h, int32_t w, int32_t winsize, int32_t fp16)
 {
     std::lock_guard<std::mutex> lk(g_tune.mu);
-    auto it = g_tune.best.find(std::make_tuple(h, w, winsize / 2, fp16 ? 1 : 0));
-    return it == g_tune.best.end() ? 0 : it->second;
+    for (int prior : {PRIOR_PLAIN, PRIOR_UPSAMPLE, PRIOR_ZERO}) {
+        auto it = g_tune.best.find(std::make_tuple(h, w, winsize / 2, fp16 ? 1 : 0, prior));
+        if (it != g_tune.best.end()) return it->second;
+    }
+    return 0;
 }
 
 const char *roi_status_str(roi_status s)

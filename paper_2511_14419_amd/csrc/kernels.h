@@ -511,7 +511,8 @@ struct IterRes {
 
 // Loads that need nothing but the pixel position: prev's coefficients at x
 // and the raw prior-flow samples (one vector, or the four coarse-grid
-// neighbours when the prior is the upsampled coarser flow).
+// neighbours when the prior is the upsampled coarser flow; those come from
+// a tile of the coarser flow staged in LDS).
 struct PxIn {
     float4 q1;   // b1x, b1y, a11, a22
     float a12;
@@ -534,17 +535,7 @@ __device__ __forceinline__ PxIn load_in(const IterArgs &a, const IterRes &rs, in
     const uint32_t c = (uint32_t)y * a.rpitch + x;
     r.q1 = PK::load4(rs.p4a, c);
     r.a12 = PK::load1(rs.p1a, c);
-    if (PRIOR == PRIOR_PLAIN) {
-        r.p00 = bload2(rs.fin, ((uint32_t)y * a.fin_pitch + x) * 8u);
-    } else if (PRIOR == PRIOR_UPSAMPLE) {
-        // pixel (y, x) of this level sits at (y/2, x/2) of the coarser grid
-        const int xc = min(x >> 1, a.wc - 1), yc = min(y >> 1, a.hc - 1);
-        const int x1 = min(xc + 1, a.wc - 1), y1 = min(yc + 1, a.hc - 1);
-        r.p00 = bload2(rs.fin, ((uint32_t)yc * a.fin_pitch + xc) * 8u);
-        r.p01 = bload2(rs.fin, ((uint32_t)yc * a.fin_pitch + x1) * 8u);
-        r.p10 = bload2(rs.fin, ((uint32_t)y1 * a.fin_pitch + xc) * 8u);
-        r.p11 = bload2(rs.fin, ((uint32_t)y1 * a.fin_pitch + x1) * 8u);
-    }
+    if (PRIOR == PRIOR_PLAIN) r.p00 = bload2(rs.fin, ((uint32_t)y * a.fin_pitch + x) * 8u);
     return r;
 }
 
@@ -626,7 +617,7 @@ __device__ __forceinline__ float2 solve2(float g11, float g12, float g22, float 
     const float tr = g11 + g22;
     if (tr == 0.f) return make_float2(0.f, 0.f);
     const float det = g11 * g22 - g12 * g12;
-    const float inv = 1.0f / fmaxf(det, eps * tr * tr);
+    const float inv = __builtin_amdgcn_rcpf(fmaxf(det, eps * tr * tr)); // v_rcp_f32: 1 ulp
     return make_float2((g22 * h1 - g12 * h2) * inv, (g11 * h2 - g12 * h1) * inv);
 }
 
@@ -648,7 +639,10 @@ __device__ __forceinline__ float2 solve2(float g11, float g12, float g22, float 
 // strip height. The chunk loop is unrolled over the NPH ring phases, which
 // makes every register-ring index a compile-time constant.
 // Replicated borders: out-of-frame rows/columns take the edge pixel's terms.
-constexpr int IT_CH = 8, IT_SEG = 8, IT_THREADS = 320, IT_HSP = IT_TW + 1;
+constexpr int IT_CH = 8, IT_THREADS = 320, IT_HSP = IT_TW + 1;
+// step 2 tasks: (channel, row, segment of IT_SEG columns), one per thread
+constexpr int IT_NSEG = IT_THREADS / (5 * IT_CH), IT_SEG = IT_TW / IT_NSEG;
+static_assert(IT_THREADS % (5 * IT_CH) == 0 && IT_TW % IT_NSEG == 0 && IT_THREADS >= 5 * IT_TW, "iteration layout");
 
 template <int R> struct IterGeom {
     static constexpr int CW = IT_TW + 2 * R;                      // columns of per-pixel terms
@@ -660,45 +654,129 @@ template <int R> struct IterGeom {
     static constexpr int GH = 5 * IT_CH * CW;                     // floats of step-1 terms
     static constexpr int HN = 5 * IT_CH * IT_HSP;                 // floats of new horizontal sums
     static constexpr int VS = 5 * IT_CH * IT_TW;                  // floats of vertical sums
+    // upsampled prior: pixel (y, x) sits at (y/2, x/2) of the coarser grid;
+    // a chunk's CW columns and IT_CH rows touch at most UC x UR coarse
+    // samples (bilinear neighbours included), staged in LDS (two buffers)
+    static constexpr int UC = CW / 2 + 2, UR = IT_CH / 2 + 2, UT = UC * UR;
+    static_assert(UT <= IT_THREADS, "one coarse sample per thread");
 };
 
 struct IterCtx {
     int x0, ys, ye, y_first, nch;
+    int xb; // first coarse column of the staged prior tile
 };
+
+// Per-thread constants: the step-1 pixel slots (row, column in the chunk,
+// clamped frame column).
+template <int R> struct IterSlots {
+    int rr[IterGeom<R>::NR1], cc[IterGeom<R>::NR1], xs[IterGeom<R>::NR1];
+    bool live[IterGeom<R>::NR1];
+};
+
+// Thread t's sample of the coarser flow for the staged tile whose first
+// coarse row is yb: tile entry t = (q, u) holds coarse pixel
+// (min(yb + q, hc - 1), min(xb + u, wc - 1)). Recomputed per chunk rather
+// than kept: registers are the iteration kernel's scarce resource.
+template <int R>
+__device__ __forceinline__ float2 up_sample(const IterArgs &a, const IterRes &rs, int yb, int xb, int t)
+{
+    const int q = t / IterGeom<R>::UC, u = t - q * IterGeom<R>::UC;
+    const int row = min(yb + q, a.hc - 1), col = min(xb + u, a.wc - 1);
+    return bload2(rs.fin, ((uint32_t)row * a.fin_pitch + col) * 8u);
+}
+
+// Whether step 1 issues the gathers of all of a thread's pixels before
+// using any (one memory round trip per chunk; more registers).
+constexpr bool iter_gather_all(int prior) { return prior != PRIOR_UPSAMPLE; }
 
 // One chunk j (ring phase P = j mod NPH) of computed rows [y_first + 8 j, + 8).
 template <typename TS, int R, int PRIOR, int P>
 __device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs, float *lds, const IterCtx &cx, int j,
-                                           const int (&rr)[IterGeom<R>::NR1], const int (&cc)[IterGeom<R>::NR1],
-                                           const bool (&live)[IterGeom<R>::NR1], const int (&xs_)[IterGeom<R>::NR1],
-                                           float (&ring)[IterGeom<R>::RING], PxIn (&pre)[IterGeom<R>::NR1])
+                                           const IterSlots<R> &sl, float (&ring)[IterGeom<R>::RING],
+                                           PxIn (&pre)[IterGeom<R>::NR1])
 {
     using G = IterGeom<R>;
-    float *gh = lds;                  // [5][IT_CH][CW]
-    float *hn = lds + G::GH;          // [5][IT_CH][IT_HSP]
-    float *vsb = lds + G::GH + G::HN; // [5][IT_CH][IT_TW]
+    float *gh = lds;                                   // [5][IT_CH][CW]
+    float *hn = lds + G::GH;                           // [5][IT_CH][IT_HSP]
+    float *vsb = lds + G::GH + G::HN;                  // [5][IT_CH][IT_TW]
+    float2 *up = (float2 *)(lds + G::GH + G::HN + G::VS); // [2][UT] coarse tiles (upsampled prior)
     const int t = threadIdx.x;
     const int cy = cx.y_first + IT_CH * j;
+    const bool more = j + 1 < cx.nch;
     // 1. per-pixel terms of rows [cy, cy + IT_CH). The position-only loads
-    //    of this chunk were issued during the previous one (pre); the next
-    //    chunk's are issued here, before this chunk's gathers are used.
+    //    of this chunk were issued during the previous one (pre). Every
+    //    gather of the chunk is issued first, then the next chunk's loads,
+    //    and only then is any of them used: one memory round trip per chunk.
+    float2 tile_next = make_float2(0.f, 0.f);
+    if constexpr (PRIOR == PRIOR_UPSAMPLE) {
+        // the four coarse neighbours of each pixel from this chunk's tile
+        const float2 *T = up + (j & 1) * G::UT;
+        const int yb = clampi(cy, 0, a.h - 1) >> 1;
 #pragma unroll
-    for (int m = 0; m < G::NR1; ++m) {
-        const PxIn cur = pre[m];
-        const PxG g = issue_gather<TS, PRIOR>(a, rs, cur, clampi(cy + rr[m], 0, a.h - 1), xs_[m], -(float)xs_[m],
-                                              (float)(a.w - 1 - xs_[m]));
-        if (j + 1 < cx.nch) pre[m] = load_in<TS, PRIOR>(a, rs, clampi(cy + IT_CH + rr[m], 0, a.h - 1), xs_[m]);
-        if (live[m]) {
-            float o[5];
-            update_terms(cur, g, o);
+        for (int m = 0; m < G::NR1; ++m) {
+            // the pixel's coarse position and its lower/right neighbours,
+            // relative to the tile: rows within [0, UR) and columns within
+            // [0, UC), since the chunk's rows and xs >= max(x0 - R, 0) span
+            // at most IT_CH rows and CW columns
+            const int y = clampi(cy + sl.rr[m], 0, a.h - 1);
+            const int yc = min(y >> 1, a.hc - 1), y1 = min(yc + 1, a.hc - 1);
+            const int xc = min(sl.xs[m] >> 1, a.wc - 1), x1 = min(xc + 1, a.wc - 1);
+            const int r0 = (yc - yb) * G::UC, r1 = (y1 - yb) * G::UC;
+            pre[m].p00 = T[r0 + xc - cx.xb];
+            pre[m].p01 = T[r0 + x1 - cx.xb];
+            pre[m].p10 = T[r1 + xc - cx.xb];
+            pre[m].p11 = T[r1 + x1 - cx.xb];
+        }
+        if (more && t < G::UT) tile_next = up_sample<R>(a, rs, clampi(cy + IT_CH, 0, a.h - 1) >> 1, cx.xb, t);
+    }
+    PxIn cur[G::NR1];
+    PxG g[G::NR1];
+    if constexpr (iter_gather_all(PRIOR)) {
 #pragma unroll
-            for (int k = 0; k < 5; ++k) gh[(k * IT_CH + rr[m]) * G::CW + cc[m]] = o[k];
+        for (int m = 0; m < G::NR1; ++m) {
+            cur[m] = pre[m];
+            g[m] = issue_gather<TS, PRIOR>(a, rs, cur[m], clampi(cy + sl.rr[m], 0, a.h - 1), sl.xs[m],
+                                           -(float)sl.xs[m], (float)(a.w - 1 - sl.xs[m]));
+        }
+        if (more) {
+#pragma unroll
+            for (int m = 0; m < G::NR1; ++m)
+                pre[m] = load_in<TS, PRIOR>(a, rs, clampi(cy + IT_CH + sl.rr[m], 0, a.h - 1), sl.xs[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < G::NR1; ++m) {
+            if (sl.live[m]) {
+                float o[5];
+                update_terms(cur[m], g[m], o);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) gh[(k * IT_CH + sl.rr[m]) * G::CW + sl.cc[m]] = o[k];
+            }
+        }
+    } else {
+        // one pixel's gathers in flight at a time (fewer registers)
+#pragma unroll
+        for (int m = 0; m < G::NR1; ++m) {
+            cur[m] = pre[m];
+            g[m] = issue_gather<TS, PRIOR>(a, rs, cur[m], clampi(cy + sl.rr[m], 0, a.h - 1), sl.xs[m],
+                                           -(float)sl.xs[m], (float)(a.w - 1 - sl.xs[m]));
+            if (more) pre[m] = load_in<TS, PRIOR>(a, rs, clampi(cy + IT_CH + sl.rr[m], 0, a.h - 1), sl.xs[m]);
+            if (sl.live[m]) {
+                float o[5];
+                update_terms(cur[m], g[m], o);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) gh[(k * IT_CH + sl.rr[m]) * G::CW + sl.cc[m]] = o[k];
+            }
         }
     }
     __syncthreads();
-    // 2. horizontal sums: task = (channel, row, 8-column segment)
+    // the next chunk's coarse tile goes to the other buffer (last read in
+    // step 1 of the previous chunk, two barriers ago)
+    if constexpr (PRIOR == PRIOR_UPSAMPLE) {
+        if (more && t < G::UT) up[((j + 1) & 1) * G::UT + t] = tile_next;
+    }
+    // 2. horizontal sums: task = (channel, row, IT_SEG-column segment)
     {
-        const int k = t >> 6, r = (t >> 3) & 7, sg = t & 7;
+        const int k = t / (IT_CH * IT_NSEG), r = (t / IT_NSEG) % IT_CH, sg = t % IT_NSEG;
         const float *src = gh + (k * IT_CH + r) * G::CW + sg * IT_SEG;
         float v[IT_SEG + 2 * R];
 #pragma unroll
@@ -718,10 +796,14 @@ __device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs,
     // 3a. thread (channel k, column c): ring update, vertical sums of the group
     const int grp = j - G::J0; // output group: rows ys + 8 grp ... + 7
     const int k = t >> 6, c = t & 63;
+    // threads beyond 5 x IT_TW (if any) have no column here
+    const bool vt = IT_THREADS == 5 * IT_TW || t < 5 * IT_TW;
+    if (vt) {
 #pragma unroll
-    for (int i = 0; i < IT_CH; ++i) ring[IT_CH * P + i] = hn[(k * IT_CH + i) * IT_HSP + c];
+        for (int i = 0; i < IT_CH; ++i) ring[IT_CH * P + i] = hn[(k * IT_CH + i) * IT_HSP + c];
+    }
     if (grp < 0) return; // (uniform) the ring is still filling
-    {
+    if (vt) {
         // ring position of row (group start - R)
         constexpr int S0 = ((IT_CH * P - IT_CH * G::J0 + G::PRE) % G::RING + G::RING) % G::RING;
         float sum = 0.f;
@@ -757,7 +839,7 @@ __global__ __launch_bounds__(IT_THREADS) void k_iter(IterArgs a, int32_t strip, 
 {
     if (a.st && blockIdx.x == 0 && threadIdx.x == 0) a.st->tau2_bits = a.t2bits;
     using G = IterGeom<R>;
-    __shared__ float lds[G::GH + G::HN + G::VS];
+    __shared__ __align__(16) float lds[G::GH + G::HN + G::VS + (PRIOR == PRIOR_UPSAMPLE ? 4 * G::UT : 0)];
 
     // XCD-aware tile order: hardware hands workgroup b to XCD b % 8, so give
     // each XCD a contiguous run of tiles (neighbours share halo columns in L2)
@@ -771,6 +853,7 @@ __global__ __launch_bounds__(IT_THREADS) void k_iter(IterArgs a, int32_t strip, 
     cx.ye = min(cx.ys + strip, a.h);
     cx.y_first = cx.ys - R - G::PRE;
     cx.nch = (cx.ye - cx.ys + IT_CH - 1) / IT_CH + G::J0;
+    cx.xb = max(cx.x0 - R, 0) >> 1;
     const uint32_t npx = (uint32_t)(a.h + 1) * a.rpitch; // packed planes carry one zero row below the frame
     IterRes rs;
     rs.p4a = make_rsrc(a.p4[0], npx * Packed<TS>::B4);
@@ -780,29 +863,33 @@ __global__ __launch_bounds__(IT_THREADS) void k_iter(IterArgs a, int32_t strip, 
     rs.fin = make_rsrc(a.fin, PRIOR == PRIOR_UPSAMPLE ? (uint32_t)a.hc * a.fin_pitch * 8u
                                                       : (uint32_t)a.h * a.fin_pitch * 8u);
     // step-1 pixels of this thread (the same slots in every chunk)
-    int rr[G::NR1], cc[G::NR1], xs_[G::NR1];
-    bool live[G::NR1];
+    IterSlots<R> sl;
 #pragma unroll
     for (int m = 0; m < G::NR1; ++m) {
         const int i = (int)threadIdx.x + IT_THREADS * m;
-        live[m] = i < IT_CH * G::CW;
-        const int ic = live[m] ? i : 0;
-        rr[m] = ic / G::CW;
-        cc[m] = ic - rr[m] * G::CW;
-        xs_[m] = clampi(cx.x0 - R + cc[m], 0, a.w - 1);
+        sl.live[m] = i < IT_CH * G::CW;
+        const int ic = sl.live[m] ? i : 0;
+        sl.rr[m] = ic / G::CW;
+        sl.cc[m] = ic - sl.rr[m] * G::CW;
+        sl.xs[m] = clampi(cx.x0 - R + sl.cc[m], 0, a.w - 1);
     }
     float ring[G::RING];
 #pragma unroll
     for (int i = 0; i < G::RING; ++i) ring[i] = 0.f;
     PxIn pre[G::NR1];
 #pragma unroll
-    for (int m = 0; m < G::NR1; ++m) pre[m] = load_in<TS, PRIOR>(a, rs, clampi(cx.y_first + rr[m], 0, a.h - 1), xs_[m]);
+    for (int m = 0; m < G::NR1; ++m)
+        pre[m] = load_in<TS, PRIOR>(a, rs, clampi(cx.y_first + sl.rr[m], 0, a.h - 1), sl.xs[m]);
+    if constexpr (PRIOR == PRIOR_UPSAMPLE) {
+        float2 *up = (float2 *)(lds + G::GH + G::HN + G::VS);
+        if ((int)threadIdx.x < G::UT)
+            up[threadIdx.x] = up_sample<R>(a, rs, clampi(cx.y_first, 0, a.h - 1) >> 1, cx.xb, (int)threadIdx.x);
+        __syncthreads();
+    }
     for (int j = 0; j < cx.nch; j += G::NPH) {
-        iter_chunk<TS, R, PRIOR, 0>(a, rs, lds, cx, j, rr, cc, live, xs_, ring, pre);
-        if (G::NPH > 1 && j + 1 < cx.nch)
-            iter_chunk<TS, R, PRIOR, 1 % G::NPH>(a, rs, lds, cx, j + 1, rr, cc, live, xs_, ring, pre);
-        if (G::NPH > 2 && j + 2 < cx.nch)
-            iter_chunk<TS, R, PRIOR, 2 % G::NPH>(a, rs, lds, cx, j + 2, rr, cc, live, xs_, ring, pre);
+        iter_chunk<TS, R, PRIOR, 0>(a, rs, lds, cx, j, sl, ring, pre);
+        if (G::NPH > 1 && j + 1 < cx.nch) iter_chunk<TS, R, PRIOR, 1 % G::NPH>(a, rs, lds, cx, j + 1, sl, ring, pre);
+        if (G::NPH > 2 && j + 2 < cx.nch) iter_chunk<TS, R, PRIOR, 2 % G::NPH>(a, rs, lds, cx, j + 2, sl, ring, pre);
     }
 }
 
