@@ -499,7 +499,10 @@ roi_status enqueue_expand(const Plan &pl, uint8_t *base, int nf, const void *con
         pitch0 = fp;
     }
     const float dc0 = dc_of(dt); // the frame's DC constant, also for denoised frames
-    for (int l = 1; l < pl.L; ++l) {
+    // with poly_n >= 5 each expansion launch also writes the next pyramid
+    // level (its tile holds the footprints); otherwise separate launches
+    const bool fused_pyr = pc.n >= 2;
+    for (int l = 1; l < pl.L && !fused_pyr; ++l) {
         const Level &src = pl.lv[l - 1], &dst = pl.lv[l];
         PyrArgs a{};
         for (int f = 0; f < nf; ++f) {
@@ -527,6 +530,13 @@ roi_status enqueue_expand(const Plan &pl, uint8_t *base, int nf, const void *con
             a.dst1[f] = base + v.r1[set[f]];
         }
         a.packed = 1;
+        if (fused_pyr && l + 1 < pl.L) {
+            const Level &nx = pl.lv[l + 1];
+            for (int f = 0; f < nf; ++f) a.pdst[f] = (double *)(base + nx.img[set[f]]);
+            a.pdst_pitch = nx.pitch;
+            a.h2 = nx.h;
+            a.w2 = nx.w;
+        }
         a.src_pitch = l == 0 ? pitch0 : v.pitch;
         a.dc = l == 0 ? dc0 : 0.0f;
         a.dplane = (int64_t)v.h * v.pitch;

@@ -2,20 +2,24 @@
 //
 // Steps (FlowRoI Method section; estimator: Farneback two-frame polynomial
 // expansion, SCIA 2003):
-//   k_pyr_down   pyramid level l -> l+1: 5x5 binomial blur at even pixels
-//   k_polyexp    local quadratic fit f ~ x^T A x + b^T x + c per pixel
+//   k_polyexp    local quadratic fit f ~ x^T A x + b^T x + c per pixel; with
+//                poly_n >= 5 the same launch also writes the next pyramid
+//                level (5x5 binomial blur at even pixels)
+//   k_pyr_down   the pyramid step on its own (stage entry point, poly_n 3)
 //   k_iter       one displacement update: prior flow (zero, given, or the
 //                2x-upsampled coarser flow), bilinear warp of next's
 //                coefficients, per-pixel normal equations, box pooling,
-//                regularised 2x2 solve, optional |d|^2 epilogue
-//   k_sel_hist   radix select of the top-q threshold on float bit patterns
-//                (|d|^2, or the saliency), the pick fused into the last block
-//   k_dilate     threshold + binary dilation into the RoI mask
+//                regularised 2x2 solve; the last launch also writes the
+//                mask stage's input (pre-mask bytes or |d|^2)
+//   k_sel_*      radix select of the top-q threshold on float bit patterns
+//                (|d|^2, or the saliency)
+//   k_dilate_bits, k_dilate   binary dilation into the RoI mask
 // Denoising pre-stage (k_denoise: median then bilateral), the saliency rule
 // (k_sal_max, k_sal: motion saliency from |d| and its gradient; k_open_close:
 // threshold, opening, closing and tile-local component labels; k_cc_border,
-// k_cc_compress: components across tiles and their areas) and the
-// adjacent-frame ensemble (k_ensemble) complete the set.
+// k_cc_compress, k_cc_keep: components across tiles, their areas, the kept
+// ones), phase-correlation stabilisation (k_ph_*, k_fft_rows, k_transpose)
+// and the adjacent-frame ensemble (k_ensemble) complete the set.
 //
 // Every kernel is a plain grid over output tiles staged through LDS. Pyramid
 // and expansion arithmetic is FP64 (storage FP32, or FP16 for the
@@ -335,6 +339,11 @@ struct PolyArgs {
     //   A_yy = H[a / (m0 m4 - m2^2)]               (V2)
     double hx[2 * PE_MAXN + 1], hy[2 * PE_MAXN + 1], hxy[2 * PE_MAXN + 1];
     double hxx[2 * PE_MAXN + 1], hyy[2 * PE_MAXN + 1];
+    // nullable (n >= 2 only): the next pyramid level of the same input,
+    // h2 x w2 FP64 with row pitch pdst_pitch, written by the same launch
+    // (the tile's input rows and columns cover its 5 x 5 footprints)
+    double *pdst[2];
+    int32_t pdst_pitch, h2, w2;
 };
 
 // The expansion's derivative filters cancel the (large) local mean of the
@@ -345,6 +354,10 @@ struct PolyArgs {
 // 8 + 2N input rows loaded together; the three vertical sums go to LDS.
 // Horizontal pass: lanes over the columns of a row, 4 rows per thread. The filters are symmetric or
 // antisymmetric, so they run on sums and differences of mirrored taps.
+// With pdst set, the launch also writes the next pyramid level from the
+// same loaded columns: binomial rows of each job, then one output per thread
+// (the taps and their order are those of the pyramid kernel, so the level
+// is bitwise the same).
 // grid: (ceil(cols/64), ceil(rows/32), frames), 512 threads; N = poly_n / 2
 constexpr int PE_TH2 = 32;
 
@@ -414,6 +427,23 @@ __global__ __launch_bounds__(PE_THREADS) void k_polyexp(PolyArgs a)
             vr[2][ROWS * qr + r][cj] = even_tap<N>(a.kv2, f[r + N], sm);
         }
     }
+    // next pyramid level: this job's column cp (relative to input column
+    // ox0 - 2) and pyramid rows oy0/2 + ROWS/2 qr + r, whose input rows
+    // 2Y-2 .. 2Y+2 are f[2r + N - 2 ...]; the vertical sums wait in
+    // registers until the expansion's horizontal pass has released vr
+    constexpr int PH = PE_TH2 / 2, PWC = PE_TW / 2 + 3;
+    const bool pyr = N >= 2 && a.pdst[0] != nullptr;
+    const int cp = cj - (N - 2);
+    const bool pjob = pyr && (int)threadIdx.x < JOBS && cp >= 0 && cp < PE_TW + 3;
+    double pv[ROWS / 2];
+    if constexpr (N >= 2) {
+        const double k0 = 1.0 / 16, k1 = 4.0 / 16, k2 = 6.0 / 16;
+#pragma unroll
+        for (int r = 0; r < ROWS / 2; ++r) {
+            const int b = 2 * r + N - 2;
+            pv[r] = k0 * f[b] + k1 * f[b + 1] + k2 * f[b + 2] + k1 * f[b + 3] + k0 * f[b + 4];
+        }
+    }
     __syncthreads();
     // horizontal pass: lane = column, so LDS reads are consecutive doubles
     // and every store instruction writes whole row segments; thread t takes
@@ -449,6 +479,27 @@ __global__ __launch_bounds__(PE_THREADS) void k_polyexp(PolyArgs a)
             for (int p = 0; p < 5; ++p)
                 st((float *)a.dst[blockIdx.z], px + p * a.dplane, a.round16 ? round16(o[p]) : o[p]);
         }
+    }
+    if constexpr (N >= 2) {
+        if (!pyr) return; // (uniform)
+        // vertical sums by column parity as in the pyramid kernel, in vr's space
+        static_assert(2 * PH * PWC <= 3 * PE_TH2 * (SW + 1), "pyramid sums fit in vr");
+        static_assert(PH * (PE_TW / 2) == PE_THREADS, "one pyramid output per thread");
+        double (*pe)[PWC] = (double (*)[PWC]) & vr[0][0][0];
+        double (*po)[PWC] = pe + PH;
+        __syncthreads(); // every read of vr done
+        if (pjob) {
+            double *col = (cp & 1) ? &po[0][1 + (cp >> 1)] : &pe[0][cp >> 1];
+#pragma unroll
+            for (int r = 0; r < ROWS / 2; ++r) col[(ROWS / 2 * qr + r) * PWC] = pv[r];
+        }
+        __syncthreads();
+        const double k0 = 1.0 / 16, k1 = 4.0 / 16, k2 = 6.0 / 16;
+        const int c = threadIdx.x & (PE_TW / 2 - 1), r = threadIdx.x / (PE_TW / 2);
+        const int X = ox0 / 2 + c, Y = oy0 / 2 + r;
+        if (X < a.w2 && Y < a.h2)
+            a.pdst[blockIdx.z][(size_t)Y * a.pdst_pitch + X] =
+                k0 * pe[r][c] + k1 * po[r][1 + c] + k2 * pe[r][c + 1] + k1 * po[r][2 + c] + k0 * pe[r][c + 2];
     }
 }
 
