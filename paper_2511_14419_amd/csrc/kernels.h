@@ -644,11 +644,17 @@ __device__ __forceinline__ PxG issue_gather(const IterArgs &a, const IterRes &rs
 //   A  = (A1(x) + A2(x + d~)) / 2,  db = -(b2(x + d~) - b1(x)) / 2 + A d~.
 __device__ __forceinline__ void update_terms(const PxIn &in, const PxG &g, float o[5])
 {
-    const float b2x = bilerp(g.v00.x, g.v01.x, g.v10.x, g.v11.x, g.fx, g.fy);
-    const float b2y = bilerp(g.v00.y, g.v01.y, g.v10.y, g.v11.y, g.fx, g.fy);
-    const float c11 = bilerp(g.v00.z, g.v01.z, g.v10.z, g.v11.z, g.fx, g.fy);
-    const float c22 = bilerp(g.v00.w, g.v01.w, g.v10.w, g.v11.w, g.fx, g.fy);
-    const float c12 = bilerp(g.w00, g.w01, g.w10, g.w11, g.fx, g.fy);
+    // bilinear weights once, then one multiply and three FMAs per channel
+    const float gx = 1.f - g.fx, gy = 1.f - g.fy;
+    const float w00 = gx * gy, w01 = g.fx * gy, w10 = gx * g.fy, w11 = g.fx * g.fy;
+    auto bl = [&](float p00, float p01, float p10, float p11) {
+        return __fmaf_rn(w11, p11, __fmaf_rn(w10, p10, __fmaf_rn(w01, p01, w00 * p00)));
+    };
+    const float b2x = bl(g.v00.x, g.v01.x, g.v10.x, g.v11.x);
+    const float b2y = bl(g.v00.y, g.v01.y, g.v10.y, g.v11.y);
+    const float c11 = bl(g.v00.z, g.v01.z, g.v10.z, g.v11.z);
+    const float c22 = bl(g.v00.w, g.v01.w, g.v10.w, g.v11.w);
+    const float c12 = bl(g.w00, g.w01, g.w10, g.w11);
     // 2A and 2 db: every term below is 4x the plain one (an exact power-of-two
     // scale), which the scale-free solve leaves unchanged bit for bit
     const float S11 = in.q1.z + c11, S22 = in.q1.w + c22, S12 = in.a12 + c12;
