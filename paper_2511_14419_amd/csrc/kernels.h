@@ -13,7 +13,7 @@
 //                mask stage's input (pre-mask bytes or |d|^2)
 //   k_sel_*      radix select of the top-q threshold on float bit patterns
 //                (|d|^2, or the saliency)
-//   k_dilate_bits, k_dilate   binary dilation into the RoI mask
+//   k_dilate_wide, k_dilate_bits, k_dilate   binary dilation into the RoI mask
 // Denoising pre-stage (k_denoise: median then bilateral), the saliency rule
 // (k_sal_max, k_sal: motion saliency from |d| and its gradient; k_open_close:
 // threshold, opening, closing and tile-local component labels; k_cc_border,
@@ -1254,6 +1254,61 @@ __global__ __launch_bounds__(256) void k_dilate_bits(DilArgs a)
             m |= e;
         }
         out[tx] = (uint64_t)(m >> r); // the tile's own 64 columns
+    }
+    __syncthreads();
+    const int x = blockIdx.x * DIL_TW + tx;
+    if (x >= a.w) return;
+    for (int yy = ty; yy < DB_TH; yy += 4) {
+        const int y = blockIdx.y * DB_TH + yy;
+        if (y >= a.h) break;
+        a.mask[(size_t)y * a.mask_pitch + x] = (uint8_t)((out[yy] >> tx) & 1);
+    }
+}
+
+// Pre-mask dilation with wide loads (frame width a multiple of 8): a tile
+// row's pre-mask bytes are read as 8-byte words, 12 per row covering columns
+// bx*64 - 16 ... bx*64 + 79, and each word becomes 8 bits with one multiply
+// (bytes are 0 or 1), so bit k of the row's 128-bit word is column
+// bx*64 - 16 + k. Words outside the frame are 0 (a word lies wholly inside
+// or outside since the width and the word columns are multiples of 8).
+// Radius up to DB_MAXR; tile 64 x 32 outputs; grid as k_dilate_bits.
+__global__ __launch_bounds__(256) void k_dilate_wide(DilArgs a)
+{
+    constexpr int WW = 12, MAXROWS = DB_TH + 2 * DB_MAXR, KW = (MAXROWS * WW + 255) / 256;
+    __shared__ uint64_t rows[MAXROWS][2];
+    __shared__ uint64_t out[DB_TH];
+    const int r = a.r, t = threadIdx.x, tx = t & 63, ty = t >> 6;
+    const int xw0 = blockIdx.x * DIL_TW - 16, oy0 = blockIdx.y * DB_TH - r;
+    const int nrows = DB_TH + 2 * r, n = nrows * WW;
+    uint8_t *rb = (uint8_t *)&rows[0][0];
+    uint64_t v[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+        // every load at a clamped, valid address (all in flight at once)
+        const int e = t + 256 * k, ly = e / WW, sgi = e - ly * WW;
+        const int y = oy0 + ly, x = xw0 + 8 * sgi;
+        const bool ok = e < n && y >= 0 && y < a.h && x >= 0 && x < a.w;
+        const int yc = min(max(y, 0), a.h - 1), xc = min(max(x, 0), a.w - 8);
+        const uint64_t w8 = *(const uint64_t *)(a.pre8 + (size_t)yc * a.w + xc);
+        v[k] = ok ? w8 : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+        const int e = t + 256 * k, ly = e / WW, sgi = e - ly * WW;
+        if (e < n) rb[ly * 16 + sgi] = (uint8_t)((v[k] * 0x0102040810204080ull) >> 56);
+    }
+    if (t < nrows) *(uint32_t *)(rb + t * 16 + WW) = 0u; // bytes 12..15 of each row
+    __syncthreads();
+    if (ty == 0 && tx < DB_TH) {
+        u128d m = 0;
+        for (int u = -r; u <= r; ++u) {
+            const int ly = tx + r + u;
+            const u128d x = ((u128d)rows[ly][1] << 64) | rows[ly][0];
+            u128d e = x;
+            for (int q = 1; q <= a.hw[u + r]; ++q) e |= (x << q) | (x >> q);
+            m |= e;
+        }
+        out[tx] = (uint64_t)(m >> 16); // the tile's own 64 columns
     }
     __syncthreads();
     const int x = blockIdx.x * DIL_TW + tx;

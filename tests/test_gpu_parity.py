@@ -127,6 +127,25 @@ def test_dilation_shapes(r, shape):
     check_mask(mask, ref_flow, ref_t2, r, shape, DELTA)
 
 
+@pytest.mark.parametrize("w", [512, 517, 64, 72, 136])
+def test_pre_mask_dilation_equals_stage_on_flow(w):
+    """roi_mask (absolute threshold: the last iteration writes pre-mask
+    bytes; widths that are multiples of 8 take the wide-load dilation) gives
+    bitwise the mask of the mask stage run on its flow (|d|^2 path), for
+    square and disc elements of radius 0 ... 16."""
+    fl = F()
+    dev = device()
+    seq = synth.sequence_u16(200, w, 2, 6, 31 + w)
+    a, b = to_dev(seq[0], dev), to_dev(seq[1], dev)
+    for r, se in [(0, 0), (1, 0), (2, 1), (5, 0), (9, 1), (16, 0), (16, 1)]:
+        p = fl.default_params(thresh=0.3, dilate_radius=r, se_shape=se)
+        flow, mask, _ = fl.roi_mask(a, b, p)
+        m2, _, _ = fl.mask_from_flow(flow, p)
+        torch.cuda.synchronize()
+        assert torch.equal(mask, m2), (w, r, se)
+        assert mask.any()
+
+
 @pytest.mark.parametrize("shape,levels,win,iters", [((333, 517), 3, 15, 3), ((97, 61), 2, 7, 2),
                                                     ((130, 70), 4, 11, 1), ((9, 7), 3, 15, 3),
                                                     ((1, 40), 1, 3, 2)])
