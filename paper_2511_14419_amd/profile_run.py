@@ -12,6 +12,10 @@ iteration kernel has a known algorithmic byte count.
 
 then ``python -m paper_2511_14419_amd.profiling traffic OUT/fetch OUT/write``.
 
+``--strip S`` forces every iteration launch to strips of S rows (the
+hardware-counter passes of ``profiling counters`` use it; 0 = the size
+heuristic).
+
 ``--mode`` selects the path: ``plain`` (default parameters), ``saliency``
 (the saliency rule: top 20 % of saliency, 3x3 opening and closing,
 components of at least 32 px), ``stabilize`` (phase-correlation
@@ -28,6 +32,7 @@ def main():
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--fp16", action="store_true")
     ap.add_argument("--mode", choices=["plain", "saliency", "stabilize", "denoise"], default="plain")
+    ap.add_argument("--strip", type=int, default=0)
     args = ap.parse_args()
 
     import torch
@@ -45,6 +50,8 @@ def main():
     seq = synth.sequence_u16(n, n, args.pairs + 1, max(1, 200 * n * n // (2048 * 2048)), 100)
     frames = [torch.from_numpy(s).to(dev) for s in seq]
     fl.autotune(0)
+    if args.strip:
+        fl.set_strip(args.strip)
     kw = {"plain": {}, "saliency": dict(rule=fl.ROI_RULE_SALIENCY, thresh_mode=1, thresh=0.2),
           "stabilize": dict(flags=fl.ROI_STABILIZE), "denoise": dict(denoise=1, sigma_range=60.0)}[args.mode]
     if args.fp16:

@@ -9,6 +9,12 @@ sampling. The result is compared with the algorithmic bytes of the same
 launches (expansion planes of both frames + prior flow + flow out + |d|^2).
 
 ``stats`` renders a ``--kernel-trace --stats`` kernel_stats.csv as a table.
+
+``counters`` reads the four counter passes of COUNTER_PASSES (one
+``rocprofv3 --pmc`` run each over ``profile_run``) and prints, per iteration
+launch of the last pair, the busy fractions of the vector ALUs, the texture
+address (TA) and data (TD) units and the L1 cache, the cache hit rates and
+the instruction counts per wave.
 """
 import csv
 import glob
@@ -111,6 +117,54 @@ def stats(stats_csv):
     return "\n".join(out)
 
 
+# Counter passes (each within one run's hardware limits: <= 8 SQ, <= 4 TCC,
+# <= 4 TCP, <= 2 TA, <= 2 TD counters).
+COUNTER_PASSES = [
+    "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_LDS SQ_INSTS_SALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY",
+    "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_VMEM SQ_ACTIVE_INST_LDS SQ_INST_CYCLES_VMEM_RD SQ_LDS_BANK_CONFLICT "
+    "SQ_WAIT_INST_LDS SQ_ACTIVE_INST_ANY SQ_THREAD_CYCLES_VALU",
+    "TA_TA_BUSY_sum TA_ADDR_STALLED_BY_TC_CYCLES_sum TD_TD_BUSY_sum TD_TC_STALL_sum TCP_TCC_READ_REQ_sum "
+    "TCP_TOTAL_CACHE_ACCESSES_sum TCP_PENDING_STALL_CYCLES_sum TCP_TCR_TCP_STALL_CYCLES_sum GRBM_GUI_ACTIVE",
+    "TCC_HIT_sum TCC_MISS_sum TCP_TCC_READ_REQ_LATENCY_sum TCP_TCP_LATENCY_sum TCP_TCP_TA_DATA_STALL_CYCLES_sum "
+    "TCP_TOTAL_READ_sum",
+]
+N_CU, N_XCD, N_SIMD, CLOCK_GHZ = 256, 8, 1024, 2.4
+
+
+def counters(pass_dirs, per_pair=9):
+    """Unit utilisation of the last pair's iteration launches from the four
+    counter passes. GRBM_GUI_ACTIVE counts cycles on each of the 8 XCDs;
+    TA/TD/TCP sums run over the 256 CUs; a wave64 FP32 VALU instruction
+    occupies a SIMD for 4 cycles."""
+    runs = [[d for d in _dispatches(p) if "k_iter" in d["name"]] for p in pass_dirs]
+    n = min(len(r) for r in runs)
+    out = []
+    for i in range(n - per_pair, n):
+        c = {}
+        for r in runs:
+            c.update({k: v for k, v in r[i].items() if k not in ("name", "grid")})
+        cyc = c["GRBM_GUI_ACTIVE"] / N_XCD
+        acc = c["TCP_TOTAL_CACHE_ACCESSES_sum"]
+        out.append({
+            "launch": i % per_pair, "grid": runs[0][i]["grid"], "kernel": runs[0][i]["name"].split("(")[0],
+            "us": round(cyc / (CLOCK_GHZ * 1e3), 1),
+            "valu_busy": round(4 * c["SQ_INSTS_VALU"] / N_SIMD / cyc, 3),
+            "ta_busy": round(c["TA_TA_BUSY_sum"] / N_CU / cyc, 3),
+            "td_busy": round(c["TD_TD_BUSY_sum"] / N_CU / cyc, 3),
+            "td_stalled_on_l1": round(c["TD_TC_STALL_sum"] / N_CU / cyc, 3),
+            "l1_pending_stall": round(c["TCP_PENDING_STALL_CYCLES_sum"] / N_CU / cyc, 3),
+            "l1_hit": round(1 - c["TCP_TCC_READ_REQ_sum"] / acc, 3),
+            "l2_hit": round(c["TCC_HIT_sum"] / (c["TCC_HIT_sum"] + c["TCC_MISS_sum"]), 3),
+            "l2_latency_cycles": round(c["TCP_TCC_READ_REQ_LATENCY_sum"] / c["TCP_TCC_READ_REQ_sum"]),
+            "l1_to_l2_MB": round(c["TCP_TCC_READ_REQ_sum"] * 128 / 1e6),
+            "lds_bank_conflict": round(c["SQ_LDS_BANK_CONFLICT"] / N_CU / cyc, 3),
+            "valu_per_wave": round(c["SQ_INSTS_VALU"] / c["SQ_WAVES"]),
+            "vmem_per_wave": round(c["SQ_INSTS_VMEM_RD"] / c["SQ_WAVES"]),
+            "lds_per_wave": round(c["SQ_INSTS_LDS"] / c["SQ_WAVES"]),
+        })
+    return out
+
+
 def load_traffic(path):
     """Measured HBM bytes per iteration launch, or None when the summary is
     missing or the kernel sources changed since the counters were taken."""
@@ -130,3 +184,6 @@ if __name__ == "__main__":
         print(json.dumps(traffic(sys.argv[2], sys.argv[3]), indent=1))
     elif sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
+    elif sys.argv[1] == "counters":
+        for row in counters(sys.argv[2:]):
+            print(json.dumps(row))
