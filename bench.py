@@ -15,7 +15,8 @@ switched on (denoising, the saliency rule, a top-fraction threshold,
 stabilisation), the mask stage alone per rule, the streaming path (previous
 frame's expansion kept resident; with the adjacent-frame ensemble), the
 batched path (16 lens streams of uneven sizes in one graph launch, FP32 and
-FP16 storage), the serving sweep, per-pair latency percentiles, the roofline
+FP16 storage, beside the same 16 pairs through one roi_mask call each), the
+serving sweep, per-pair latency percentiles, the roofline
 of the dominant kernel (the iteration kernel, timed with HIP events on its
 own stream inside the timed region) and the FP64 oracle timed on the host
 on one 2048x2048 pair.
@@ -296,8 +297,26 @@ def bench_batched(fl, dev, args, fp16):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     px = sum(x.numel() for x in prevs)
+    # the same pairs through the plain per-pair path, one roi_mask call each
+    wss = [fl.alloc_workspace(fl.workspace_size(x.shape[0], x.shape[1], fl.ROI_U16, p), dev) for x in prevs]
+
+    def one_by_one():
+        for i in range(len(prevs)):
+            fl.roi_mask(prevs[i], nexts[i], p, flow=flows[i], mask=masks[i], ws=wss[i])
+    one_by_one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        one_by_one()
+    torch.cuda.synchronize()
+    dts = (time.perf_counter() - t0) / reps
+    del wss
+    fl.roi_mask_batched(pairs, fl.ROI_U16, p, ws)  # leave the batched results in flows / masks
+    torch.cuda.synchronize()
     r = {"pairs": len(prevs), "ms_per_launch": round(dt * 1e3, 3), "mpx_per_s": round(px / dt / 1e6, 1),
-         "frames_2048_equiv_per_s": round(px / dt / (H * W), 2), "storage": "f16" if fp16 else "f32"}
+         "frames_2048_equiv_per_s": round(px / dt / (H * W), 2), "storage": "f16" if fp16 else "f32",
+         "same_pairs_per_pair_calls": {"ms": round(dts * 1e3, 3), "frames_2048_equiv_per_s": round(px / dts / (H * W), 2)},
+         "speedup_vs_per_pair_calls": round(dts / dt, 3)}
     if fp16 and not args.no_cpu_baseline:
         r["error_vs_oracle"] = fp16_error(seqs, flows, masks)
     log("batched %s: %s" % (r["storage"], r))

@@ -253,9 +253,12 @@ typedef struct roi_pair {
 size_t roi_batched_workspace_size(int32_t n, const roi_pair *pairs, roi_dtype dtype, const roi_params *p);
 
 /* All n pairs through the whole path. Each pair's result is the one roi_mask
- * gives for it alone (the same kernels, the same per-pixel arithmetic).
- * The launch sequence for a given (pairs, dtype, params, ws) is captured
- * into a HIP graph on first use and replayed afterwards. n in 1..256. */
+ * gives for it alone (the same per-pixel arithmetic, bit for bit). The
+ * expansions and the mask stages run as independent per-pair branches; each
+ * level and update of the flow is one launch over up to 16 pairs at once,
+ * so the coarse levels of many pairs fill the GPU together. The launch
+ * sequence for a given (pairs, dtype, params, ws) is captured into a HIP
+ * graph on first use and replayed afterwards. n in 1..256. */
 roi_status roi_mask_batched(int32_t n, const roi_pair *pairs, roi_dtype dtype, const roi_params *p,
                             void *ws, size_t ws_bytes, void *stream);
 

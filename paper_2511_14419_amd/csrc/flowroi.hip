@@ -718,6 +718,78 @@ roi_status launch_iter(const IterArgs &a, bool fp16, hipStream_t s, Bracket *cal
     return ok ? ROI_OK : ROI_EDEVICE;
 }
 
+// Several pairs' launches of one level and update, IT_MULTI pairs per grid
+// (k_iter_multi). One strip height per grid: the tallest candidate that
+// still gives >= 512 workgroups (2 per CU) over the group, since many pairs
+// together fill the chip with taller, cheaper strips.
+int multi_strip(const IterArgs *as, int n)
+{
+    auto wgs = [&](int st) {
+        long t = 0;
+        for (int i = 0; i < n; ++i) t += (long)((as[i].w + IT_TW - 1) / IT_TW) * ((as[i].h + st - 1) / st);
+        return t;
+    };
+    int strip = 256;
+    while (strip > 8 && wgs(strip) < 512) strip /= 2;
+    return strip;
+}
+
+static_assert(sizeof(IterMulti) <= 4096, "kernel argument size");
+
+template <typename TS, int R, int PRIOR>
+void launch_multi_r(const IterMulti &m, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_iter_multi<TS, R, PRIOR>), dim3(m.tile0[m.n]), dim3(IT_THREADS), 0, s, m);
+}
+
+template <typename TS, int PRIOR>
+void launch_multi_p(const IterMulti &m, int R, hipStream_t s)
+{
+    switch (R) {
+    case 0: launch_multi_r<TS, 0, PRIOR>(m, s); break;
+    case 1: launch_multi_r<TS, 1, PRIOR>(m, s); break;
+    case 2: launch_multi_r<TS, 2, PRIOR>(m, s); break;
+    case 3: launch_multi_r<TS, 3, PRIOR>(m, s); break;
+    case 4: launch_multi_r<TS, 4, PRIOR>(m, s); break;
+    case 5: launch_multi_r<TS, 5, PRIOR>(m, s); break;
+    case 6: launch_multi_r<TS, 6, PRIOR>(m, s); break;
+    default: launch_multi_r<TS, 7, PRIOR>(m, s); break;
+    }
+}
+
+template <typename TS>
+void launch_multi_t(const IterMulti &m, int R, int prior, hipStream_t s)
+{
+    if (prior == PRIOR_ZERO) launch_multi_p<TS, PRIOR_ZERO>(m, R, s);
+    else if (prior == PRIOR_PLAIN) launch_multi_p<TS, PRIOR_PLAIN>(m, R, s);
+    else launch_multi_p<TS, PRIOR_UPSAMPLE>(m, R, s);
+}
+
+// All arguments share the level index, update, prior mode and window.
+roi_status launch_iter_multi(const std::vector<IterArgs> &as, bool fp16, hipStream_t s)
+{
+    for (size_t g0 = 0; g0 < as.size(); g0 += IT_MULTI) {
+        IterMulti m{};
+        m.n = (int32_t)std::min<size_t>(IT_MULTI, as.size() - g0);
+        const int strip = multi_strip(&as[g0], m.n);
+        int t = 0;
+        for (int i = 0; i < m.n; ++i) {
+            const IterArgs &a = as[g0 + i];
+            m.a[i] = a;
+            m.strip[i] = strip;
+            m.nx[i] = (a.w + IT_TW - 1) / IT_TW;
+            m.ntiles[i] = m.nx[i] * ((a.h + strip - 1) / strip);
+            m.tile0[i] = t;
+            t += (m.ntiles[i] + 7) & ~7;
+        }
+        m.tile0[m.n] = t;
+        if (fp16) launch_multi_t<__half>(m, as[g0].R, as[g0].prior, s);
+        else launch_multi_t<float>(m, as[g0].R, as[g0].prior, s);
+        if (hipGetLastError() != hipSuccess) return ROI_EDEVICE;
+    }
+    return ROI_OK;
+}
+
 // Buffers of the stage from |d|^2 to the mask. m2 (pitch m2_pitch) holds
 // |d|^2; under the saliency rule sal (h rows of sal_pitch floats), lab and
 // area (h w int32 each) are scratch, and the component links reuse m2.
@@ -856,104 +928,102 @@ roi_status enqueue_mask(const MaskBufs &mb, SelState *slot, int h, int w, const 
     return ROI_OK;
 }
 
-// Coarse-to-fine iterations from expansion set `s1` (prev) to `s2` (next),
-// then the threshold and dilation into `mask` (skipped when mask is NULL).
-roi_status enqueue_flow(const Plan &pl, uint8_t *base, SelState *slot, int s1, int s2, int h, int w,
-                        const roi_params *p, float *flow, uint8_t *mask, hipStream_t s)
+// The absolute threshold's |d|^2 bits (the pre-mask of the last update).
+uint32_t abs_t2bits(const roi_params *p)
+{
+    const float t2 = p->thresh * p->thresh;
+    uint32_t b = 0;
+    std::memcpy(&b, &t2, 4);
+    return b;
+}
+
+// An absolute threshold on |d| is known before the flow: the last update
+// writes the pre-mask bytes and records the threshold itself.
+bool pre8_mode_of(const roi_params *p) { return p->rule == ROI_RULE_MAGNITUDE && p->thresh_mode == ROI_THRESH_ABS; }
+
+// Arguments of update `it` at level l, from expansion set s1 (prev) to s2
+// (next). Flow buffers ping-pong between the level's fa and fb (the caller's
+// flow at level 0) so that the last update of every level lands in fb / flow.
+IterArgs make_iter_args(const Plan &pl, uint8_t *base, SelState *slot, int s1, int s2, int w, const roi_params *p,
+                        float *flow, uint8_t *mask, int l, int it)
 {
     const bool init = (p->flags & ROI_USE_INITIAL_FLOW) != 0;
     const int L = pl.L, n = p->iterations;
-    // an absolute threshold on |d| is known before the flow: the last update
-    // writes the pre-mask bytes and records the threshold itself
-    const bool pre8_mode = p->rule == ROI_RULE_MAGNITUDE && p->thresh_mode == ROI_THRESH_ABS;
-    uint32_t t2bits = 0;
-    {
-        const float t2 = p->thresh * p->thresh;
-        std::memcpy(&t2bits, &t2, 4);
+    const Level &v = pl.lv[l];
+    float2 *X = (float2 *)(base + v.fa);
+    float2 *Y = l == 0 ? (float2 *)flow : (float2 *)(base + v.fb);
+    const int xp = v.pitch, yp = l == 0 ? w : v.pitch;
+    auto out_of = [&](int k, int &pitch) -> float2 * {
+        const bool toY = ((n - 1 - k) % 2) == 0;
+        pitch = toY ? yp : xp;
+        return toY ? Y : X;
+    };
+    IterArgs a{};
+    a.p4[0] = base + v.r4[s1];
+    a.p1[0] = base + v.r1[s1];
+    a.p4[1] = base + v.r4[s2];
+    a.p1[1] = base + v.r1[s2];
+    a.rpitch = v.pitch;
+    a.h = v.h;
+    a.w = v.w;
+    if (it > 0) {
+        a.prior = PRIOR_PLAIN;
+        a.fin = out_of(it - 1, a.fin_pitch);
+    } else if (l < L - 1) {
+        const Level &c = pl.lv[l + 1]; // its last update wrote fb
+        a.prior = PRIOR_UPSAMPLE;
+        a.fin = (const float2 *)(base + c.fb);
+        a.fin_pitch = c.pitch;
+        a.hc = c.h;
+        a.wc = c.w;
+    } else if (init) {
+        a.prior = PRIOR_PLAIN;
+        a.fin = (const float2 *)(base + pl.init_off);
+        a.fin_pitch = pl.lv[L - 1].pitch;
+    } else {
+        a.prior = PRIOR_ZERO;
     }
-    const Level &c = pl.lv[L - 1];
-    if (init) {
-        InitArgs a{};
-        a.src = (const float2 *)flow;
-        a.src_pitch = w;
-        a.h = h;
-        a.w = w;
-        a.dst = (float2 *)(base + pl.init_off);
-        a.dst_pitch = c.pitch;
-        a.hl = c.h;
-        a.wl = c.w;
-        a.stride = 1 << (L - 1);
-        dim3 g((c.w + 63) / 64, (c.h + 3) / 4);
-        hipLaunchKernelGGL(k_init_flow, g, dim3(256), 0, s, a);
-        LAUNCH_CHECK();
-    }
-    const float2 *coarse = nullptr;
-    int coarse_pitch = 0, hc = 0, wc = 0;
-    Bracket call; // timing mode 2: the call's run of iteration launches
-    call.open(2, s);
-    for (int l = L - 1; l >= 0; --l) {
-        const Level &v = pl.lv[l];
-        float2 *X = (float2 *)(base + v.fa);
-        float2 *Y = l == 0 ? (float2 *)flow : (float2 *)(base + v.fb);
-        const int xp = v.pitch, yp = l == 0 ? w : v.pitch;
-        const float2 *prev_out = nullptr;
-        int prev_pitch = 0;
-        for (int it = 0; it < n; ++it) {
-            IterArgs a{};
-            a.p4[0] = base + v.r4[s1];
-            a.p1[0] = base + v.r1[s1];
-            a.p4[1] = base + v.r4[s2];
-            a.p1[1] = base + v.r1[s2];
-            a.rpitch = v.pitch;
-            a.h = v.h;
-            a.w = v.w;
-            if (it > 0) {
-                a.prior = PRIOR_PLAIN;
-                a.fin = prev_out;
-                a.fin_pitch = prev_pitch;
-            } else if (l < L - 1) {
-                a.prior = PRIOR_UPSAMPLE;
-                a.fin = coarse;
-                a.fin_pitch = coarse_pitch;
-                a.hc = hc;
-                a.wc = wc;
-            } else if (init) {
-                a.prior = PRIOR_PLAIN;
-                a.fin = (const float2 *)(base + pl.init_off);
-                a.fin_pitch = c.pitch;
-            } else {
-                a.prior = PRIOR_ZERO;
-            }
-            const bool toY = ((n - 1 - it) % 2) == 0;
-            a.fout = toY ? Y : X;
-            a.fout_pitch = toY ? yp : xp;
-            a.R = p->winsize / 2;
-            a.eps = p->eps;
-            if (l == 0 && it == n - 1 && mask) {
-                if (pre8_mode) {
-                    a.pre8 = base + pl.m2_off;
-                    a.t2bits = t2bits;
-                    a.st = slot;
-                } else {
-                    a.m2 = (float *)(base + pl.m2_off);
-                    a.m2_pitch = pl.lv[0].pitch;
-                }
-            }
-            roi_status st = launch_iter(a, pl.fp16, s, &call);
-            if (st != ROI_OK) {
-                call.close();
-                return st;
-            }
-            prev_out = a.fout;
-            prev_pitch = a.fout_pitch;
+    a.fout = out_of(it, a.fout_pitch);
+    a.R = p->winsize / 2;
+    a.eps = p->eps;
+    if (l == 0 && it == n - 1 && mask) {
+        if (pre8_mode_of(p)) {
+            a.pre8 = base + pl.m2_off;
+            a.t2bits = abs_t2bits(p);
+            a.st = slot;
+        } else {
+            a.m2 = (float *)(base + pl.m2_off);
+            a.m2_pitch = pl.lv[0].pitch;
         }
-        coarse = prev_out;
-        coarse_pitch = prev_pitch;
-        hc = v.h;
-        wc = v.w;
     }
-    call.close();
-    if (!mask) return ROI_OK;
+    return a;
+}
+
+// The caller's initial flow, subsampled to the coarsest level.
+void enqueue_init_flow(const Plan &pl, uint8_t *base, int h, int w, const roi_params *p, const float *flow,
+                       hipStream_t s)
+{
+    if (!(p->flags & ROI_USE_INITIAL_FLOW)) return;
+    const int L = pl.L;
+    const Level &c = pl.lv[L - 1];
+    InitArgs a{};
+    a.src = (const float2 *)flow;
+    a.src_pitch = w;
+    a.h = h;
+    a.w = w;
+    a.dst = (float2 *)(base + pl.init_off);
+    a.dst_pitch = c.pitch;
+    a.hl = c.h;
+    a.wl = c.w;
+    a.stride = 1 << (L - 1);
+    dim3 g((c.w + 63) / 64, (c.h + 3) / 4);
+    hipLaunchKernelGGL(k_init_flow, g, dim3(256), 0, s, a);
+}
+
+// Threshold and dilation into `mask` after the last update.
+roi_status enqueue_mask_stage(const Plan &pl, uint8_t *base, SelState *slot, int h, int w, const roi_params *p,
+                              uint8_t *mask, hipStream_t s)
+{
     MaskBufs mb{};
     mb.m2 = (float *)(base + pl.m2_off);
     mb.m2_pitch = pl.lv[0].pitch;
@@ -965,8 +1035,32 @@ roi_status enqueue_flow(const Plan &pl, uint8_t *base, SelState *slot, int s1, i
     mb.lab = (int32_t *)(base + pl.lv[0].fa + (size_t)pl.lv[0].h * pl.lv[0].pitch * sizeof(float));
     mb.area = (int32_t *)(base + pl.area_off);
     mb.maxs = (uint32_t *)(base + pl.max_off);
-    mb.pre8 = pre8_mode;
+    mb.pre8 = pre8_mode_of(p);
     return enqueue_mask(mb, slot, h, w, p, mask, nullptr, s);
+}
+
+// Coarse-to-fine iterations from expansion set `s1` (prev) to `s2` (next),
+// then the threshold and dilation into `mask` (skipped when mask is NULL).
+roi_status enqueue_flow(const Plan &pl, uint8_t *base, SelState *slot, int s1, int s2, int h, int w,
+                        const roi_params *p, float *flow, uint8_t *mask, hipStream_t s)
+{
+    enqueue_init_flow(pl, base, h, w, p, flow, s);
+    LAUNCH_CHECK();
+    Bracket call; // timing mode 2: the call's run of iteration launches
+    call.open(2, s);
+    for (int l = pl.L - 1; l >= 0; --l) {
+        for (int it = 0; it < p->iterations; ++it) {
+            const IterArgs a = make_iter_args(pl, base, slot, s1, s2, w, p, flow, mask, l, it);
+            roi_status st = launch_iter(a, pl.fp16, s, &call);
+            if (st != ROI_OK) {
+                call.close();
+                return st;
+            }
+        }
+    }
+    call.close();
+    if (!mask) return ROI_OK;
+    return enqueue_mask_stage(pl, base, slot, h, w, p, mask, s);
 }
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
@@ -1001,7 +1095,7 @@ DeviceStreams *device_streams(int naux)
         if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess) return nullptr;
         ds.aux.push_back(a);
     }
-    while ((int)ds.ev.size() < naux + 1) {
+    while ((int)ds.ev.size() < 2 * naux + 2) {
         hipEvent_t e;
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
         ds.ev.push_back(e);
@@ -1345,17 +1439,6 @@ size_t roi_batched_workspace_size(int32_t n, const roi_pair *pairs, roi_dtype dt
     return total;
 }
 
-static roi_status enqueue_pair(const roi_pair &q, roi_dtype dtype, const roi_params *p, uint8_t *base,
-                               SelState *slot, PhaseState *ph, hipStream_t s)
-{
-    const Plan pl = make_plan(q.h, q.w, p);
-    const void *frames[2] = {q.prev, q.next};
-    const int sets[2] = {0, 1};
-    roi_status st = enqueue_expand(pl, base, 2, frames, q.pitch, dtype, p, sets, s, ph);
-    if (st != ROI_OK) return st;
-    return enqueue_flow(pl, base, slot, 0, 1, q.h, q.w, p, q.flow, q.mask, s);
-}
-
 roi_status roi_mask_batched(int32_t n, const roi_pair *pairs, roi_dtype dtype, const roi_params *p, void *ws,
                             size_t ws_bytes, void *stream)
 {
@@ -1392,18 +1475,65 @@ roi_status roi_mask_batched(int32_t n, const roi_pair *pairs, roi_dtype dtype, c
         roi_status st = ROI_OK;
         // fork: every auxiliary stream waits on the capture origin, pairs are
         // spread over them so the graph holds independent per-pair chains
+        // 1. per pair on the auxiliary streams: pyramid and expansions (with
+        //    denoising / stabilisation) and the initial flow
         hipEventRecord(ds->ev[0], cs);
         for (int k = 0; k < naux; ++k) hipStreamWaitEvent(ds->aux[k], ds->ev[0], 0);
+        struct Job {
+            Plan pl;
+            uint8_t *base;
+            int i;
+        };
+        std::vector<Job> jobs;
         uint8_t *base = (uint8_t *)ws + HDR_BYTES;
         for (int i = 0; i < n && st == ROI_OK; ++i) {
             const roi_pair &q = pairs[i];
             if (q.h == 0 || q.w == 0) continue;
-            st = enqueue_pair(q, dtype, p, base, (SelState *)ws + i, phase_slot(ws, i), ds->aux[i % naux]);
-            base += make_plan(q.h, q.w, p).bytes;
+            const Plan pl = make_plan(q.h, q.w, p);
+            const void *frames[2] = {q.prev, q.next};
+            const int sets[2] = {0, 1};
+            hipStream_t as = ds->aux[i % naux];
+            st = enqueue_expand(pl, base, 2, frames, q.pitch, dtype, p, sets, as, phase_slot(ws, i));
+            if (st == ROI_OK) enqueue_init_flow(pl, base, q.h, q.w, p, q.flow, as);
+            jobs.push_back({pl, base, i});
+            base += pl.bytes;
         }
         for (int k = 0; k < naux; ++k) {
             hipEventRecord(ds->ev[k + 1], ds->aux[k]);
             hipStreamWaitEvent(cs, ds->ev[k + 1], 0);
+        }
+        // 2. every coarse level and update of all pairs in one grid (per
+        //    IT_MULTI pairs): the coarse levels of many pairs fill the chip
+        //    together
+        const bool fp16 = (p->flags & ROI_FP16_STORAGE) != 0;
+        for (int l = p->levels - 1; l >= 1 && st == ROI_OK && !jobs.empty(); --l) {
+            for (int it = 0; it < p->iterations && st == ROI_OK; ++it) {
+                std::vector<IterArgs> as;
+                for (const Job &jb : jobs) {
+                    const roi_pair &q = pairs[jb.i];
+                    as.push_back(make_iter_args(jb.pl, jb.base, (SelState *)ws + jb.i, 0, 1, q.w, p, q.flow, q.mask,
+                                                l, it));
+                }
+                st = launch_iter_multi(as, fp16, cs);
+            }
+        }
+        // 3. per pair on the auxiliary streams: the full-resolution updates
+        //    (each fills the chip alone), threshold and dilation
+        hipEventRecord(ds->ev[naux + 1], cs);
+        for (int k = 0; k < naux; ++k) hipStreamWaitEvent(ds->aux[k], ds->ev[naux + 1], 0);
+        for (const Job &jb : jobs) {
+            if (st != ROI_OK) break;
+            const roi_pair &q = pairs[jb.i];
+            hipStream_t as = ds->aux[jb.i % naux];
+            for (int it = 0; it < p->iterations && st == ROI_OK; ++it)
+                st = launch_iter(make_iter_args(jb.pl, jb.base, (SelState *)ws + jb.i, 0, 1, q.w, p, q.flow, q.mask, 0, it),
+                                 fp16, as, nullptr);
+            if (st == ROI_OK)
+                st = enqueue_mask_stage(jb.pl, jb.base, (SelState *)ws + jb.i, q.h, q.w, p, q.mask, as);
+        }
+        for (int k = 0; k < naux; ++k) {
+            hipEventRecord(ds->ev[naux + 2 + k], ds->aux[k]);
+            hipStreamWaitEvent(cs, ds->ev[naux + 2 + k], 0);
         }
         hipGraph_t graph = nullptr;
         const hipError_t ce = hipStreamEndCapture(cs, &graph);

@@ -891,16 +891,21 @@ __device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs,
     // no barrier: vs is next written by 3a of a later chunk, two barriers away
 }
 
-template <typename TS, int R, int PRIOR>
-__global__ __launch_bounds__(IT_THREADS) void k_iter(IterArgs a, int32_t strip, int32_t nx, int32_t ntiles)
-{
-    if (a.st && blockIdx.x == 0 && threadIdx.x == 0) a.st->tau2_bits = a.t2bits;
-    using G = IterGeom<R>;
-    __shared__ __align__(16) float lds[G::GH + G::HN + G::VS + (PRIOR == PRIOR_UPSAMPLE ? 4 * G::UT : 0)];
+template <int R, int PRIOR> struct IterLds {
+    static constexpr int FLOATS = IterGeom<R>::GH + IterGeom<R>::HN + IterGeom<R>::VS +
+                                  (PRIOR == PRIOR_UPSAMPLE ? 4 * IterGeom<R>::UT : 0);
+};
 
+// One workgroup's strip: tile b (in launch order) of a level of `ntiles`
+// tiles, nx per row of strips.
+template <typename TS, int R, int PRIOR>
+__device__ __forceinline__ void iter_tile(const IterArgs &a, int32_t strip, int32_t nx, int32_t ntiles, int b,
+                                          float *lds)
+{
+    if (a.st && b == 0 && threadIdx.x == 0) a.st->tau2_bits = a.t2bits;
+    using G = IterGeom<R>;
     // XCD-aware tile order: hardware hands workgroup b to XCD b % 8, so give
     // each XCD a contiguous run of tiles (neighbours share halo columns in L2)
-    int b = blockIdx.x;
     const int n8 = ntiles & ~7;
     if (b < n8) b = (b & 7) * (n8 >> 3) + (b >> 3);
     const int tx = b % nx, ty = b / nx;
@@ -948,6 +953,36 @@ __global__ __launch_bounds__(IT_THREADS) void k_iter(IterArgs a, int32_t strip, 
         if (G::NPH > 1 && j + 1 < cx.nch) iter_chunk<TS, R, PRIOR, 1 % G::NPH>(a, rs, lds, cx, j + 1, sl, ring, pre);
         if (G::NPH > 2 && j + 2 < cx.nch) iter_chunk<TS, R, PRIOR, 2 % G::NPH>(a, rs, lds, cx, j + 2, sl, ring, pre);
     }
+}
+
+template <typename TS, int R, int PRIOR>
+__global__ __launch_bounds__(IT_THREADS) void k_iter(IterArgs a, int32_t strip, int32_t nx, int32_t ntiles)
+{
+    __shared__ __align__(16) float lds[IterLds<R, PRIOR>::FLOATS];
+    iter_tile<TS, R, PRIOR>(a, strip, nx, ntiles, blockIdx.x, lds);
+}
+
+// Several pairs' launches of one level and iteration in one grid: pair i
+// owns workgroups [tile0[i], tile0[i+1]), a run rounded up to a multiple of
+// 8 so that each pair keeps the XCD-aware order (workgroups past a pair's
+// own tiles exit at once). All pairs share the prior mode and window.
+constexpr int IT_MULTI = 16;
+struct IterMulti {
+    IterArgs a[IT_MULTI];
+    int32_t strip[IT_MULTI], nx[IT_MULTI], ntiles[IT_MULTI];
+    int32_t tile0[IT_MULTI + 1];
+    int32_t n;
+};
+
+template <typename TS, int R, int PRIOR>
+__global__ __launch_bounds__(IT_THREADS) void k_iter_multi(IterMulti m)
+{
+    __shared__ __align__(16) float lds[IterLds<R, PRIOR>::FLOATS];
+    int i = 0;
+    while (i + 1 < m.n && (int)blockIdx.x >= m.tile0[i + 1]) ++i; // (uniform)
+    const int b = (int)blockIdx.x - m.tile0[i];
+    if (b >= m.ntiles[i]) return;
+    iter_tile<TS, R, PRIOR>(m.a[i], m.strip[i], m.nx[i], m.ntiles[i], b, lds);
 }
 
 // ---------------------------------------------------------------- top-q select
