@@ -28,11 +28,22 @@ KERNEL_SOURCES = [os.path.join(PKG, "csrc", "kernels.h")]
 COPY_BYTES = 256 << 20
 
 
+# The iteration kernel's source: the section of kernels.h from its own
+# header line to the next section's (packed-plane loaders and buffer
+# descriptors it uses sit above it and are hashed too).
+ITER_SECTION = ("// ---------------------------------------------------------------- displacement update",
+                "// ---------------------------------------------------------------- top-q select")
+
+
 def kernel_source_sha():
+    """SHA-256 of the source the iteration kernel is built from: kernels.h
+    up to the end of its section (everything after it is other kernels)."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
         with open(p, "rb") as fh:
-            h.update(fh.read())
+            text = fh.read().decode()
+        end = text.find(ITER_SECTION[1])
+        h.update((text if end < 0 else text[:end]).encode())
     return h.hexdigest()
 
 
