@@ -345,6 +345,34 @@ def test_batched_equals_single_calls():
                 assert fl.read_tau2(ws, i) == np.float32(1.0)
 
 
+def test_batched_more_pairs_than_one_grid_holds():
+    """19 pairs (two multi-pair grids of coarse-level updates: 16 + 3) of
+    uneven sizes with the top-fraction threshold: every pair equals its
+    single call bit for bit, on capture and on replay."""
+    dev = device()
+    fl = F()
+    rng = np.random.default_rng(5)
+    sizes = [(int(rng.integers(70, 200)), int(rng.integers(70, 200))) for _ in range(19)]
+    pr = _pairs(dev, sizes, seed0=90)
+    p = fl.default_params(thresh_mode=1, thresh=0.2)
+    single = []
+    for a, b in pr:
+        f, m, _ = fl.roi_mask(a, b, p)
+        single.append((f.clone(), m.clone()))
+    flows = [torch.empty((a.shape[0], a.shape[1], 2), device=dev) for a, _ in pr]
+    masks = [torch.empty(a.shape, dtype=torch.uint8, device=dev) for a, _ in pr]
+    prevs, nexts = [a for a, _ in pr], [b for _, b in pr]
+    pairs = fl.make_pairs(prevs, nexts, flows, masks)
+    ws = fl.alloc_workspace(fl.batched_workspace_size(pairs, fl.ROI_U16, p), dev)
+    for rep in range(2):
+        for f in flows:
+            f.fill_(float("nan"))
+        fl.roi_mask_batched(pairs, fl.ROI_U16, p, ws)
+        torch.cuda.synchronize()
+        for i, ((sf, sm), f, m) in enumerate(zip(single, flows, masks)):
+            assert torch.equal(sf, f) and torch.equal(sm, m), (rep, i, sizes[i])
+
+
 def test_batched_replay_sees_new_frames():
     dev = device()
     fl = F()
