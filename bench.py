@@ -56,7 +56,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline path only")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-streams", type=int, default=64)
-    ap.add_argument("--serve-rates", type=str, default="8,256,1024,1536,2048,2560,3072")
+    ap.add_argument("--serve-rates", type=str, default="8,256,1024,1536,2048,2560,3072,3584")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the frame streams "

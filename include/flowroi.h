@@ -288,9 +288,11 @@ void roi_stream_destroy(void *ctx);
 roi_status roi_stream_read_shift(void *ctx, int32_t *sy, int32_t *sx, float *peak, void *stream);
 
 /* Several stream contexts advanced together: frames[i] is pushed into
- * ctxs[i], all in one batched launch sequence on `stream`. status[i] gets
- * ROI_PRIMED or ROI_OK per context. Contexts must share dtype and params.
- * n in 1..256. */
+ * ctxs[i], all in one batched launch sequence on `stream`; the coarse-level
+ * updates of all contexts that produce a flow share grids of up to 16.
+ * status[i] gets ROI_PRIMED or ROI_OK per context, and each result is the
+ * one roi_stream_push gives. Contexts must share dtype and params and be
+ * distinct (ROI_EINVAL otherwise). n in 1..256. */
 roi_status roi_stream_push_many(int32_t n, void *const *ctxs, const void *const *frames,
                                 const int64_t *pitches, float *const *flows, uint8_t *const *masks,
                                 int32_t *status, void *stream);

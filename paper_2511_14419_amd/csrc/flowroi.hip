@@ -1633,6 +1633,24 @@ void roi_stream_destroy(void *ctx)
     delete c;
 }
 
+// Union of this mask with the stream's previous masks, then remember it.
+static roi_status enqueue_ensemble(roi_stream_ctx *c, uint8_t *mask, hipStream_t s)
+{
+    const size_t n = (size_t)c->h * c->w, slot = align_up(n, ALIGN);
+    const int K = c->p.adjacent;
+    EnsembleArgs ea{};
+    ea.mask = mask;
+    ea.store = c->hist + (size_t)c->hist_pos * slot;
+    ea.n = c->hist_count;
+    for (int k = 0; k < ea.n; ++k) ea.prev[k] = c->hist + (size_t)((c->hist_pos - 1 - k + K) % K) * slot;
+    ea.count = (int64_t)n;
+    hipLaunchKernelGGL(k_ensemble, dim3((unsigned)((n + 4095) / 4096)), dim3(256), 0, s, ea);
+    LAUNCH_CHECK();
+    c->hist_pos = (c->hist_pos + 1) % K;
+    if (c->hist_count < K) c->hist_count += 1;
+    return ROI_OK;
+}
+
 static roi_status stream_push_one(roi_stream_ctx *c, const void *frame, int64_t pitch, float *flow, uint8_t *mask,
                                   hipStream_t s)
 {
@@ -1653,20 +1671,98 @@ static roi_status stream_push_one(roi_stream_ctx *c, const void *frame, int64_t 
     st = enqueue_flow(c->plan, base, (SelState *)c->buf, c->cur, nxt, c->h, c->w, &c->p, flow, mask, s);
     if (st != ROI_OK) return st;
     c->cur = nxt;
-    if (c->p.adjacent > 0 && mask) {
-        // union with the stream's previous masks, then remember this one
-        const size_t n = (size_t)c->h * c->w, slot = align_up(n, ALIGN);
-        const int K = c->p.adjacent;
-        EnsembleArgs ea{};
-        ea.mask = mask;
-        ea.store = c->hist + (size_t)c->hist_pos * slot;
-        ea.n = c->hist_count;
-        for (int k = 0; k < ea.n; ++k) ea.prev[k] = c->hist + (size_t)((c->hist_pos - 1 - k + K) % K) * slot;
-        ea.count = (int64_t)n;
-        hipLaunchKernelGGL(k_ensemble, dim3((unsigned)((n + 4095) / 4096)), dim3(256), 0, s, ea);
+    if (c->p.adjacent > 0 && mask) return enqueue_ensemble(c, mask, s);
+    return ROI_OK;
+}
+
+// Pushes to several stream contexts (same parameters) as one batch: each
+// context's expansion, full-resolution updates, mask stage and ensemble run
+// on its own stream ss[i], while the coarse-level updates of all contexts
+// that produce a flow share multi-pair grids on stream js (joined and forked
+// with the events in evs, one per distinct stream and direction; at least
+// 2 * SRV_FORK_MAX). The per-pixel arithmetic is that of stream_push_one.
+constexpr int SRV_FORK_MAX = 8;
+static roi_status stream_push_batch(int n, roi_stream_ctx *const *cs, const void *const *frames, const int64_t *pitches,
+                                    float *const *flows, uint8_t *const *masks, int32_t *status, const hipStream_t *ss,
+                                    hipStream_t js, hipEvent_t *evs)
+{
+    std::vector<int> jobs;
+    std::vector<int> nxt(n, 0);
+    for (int i = 0; i < n; ++i) {
+        roi_stream_ctx *c = cs[i];
+        if (!frames[i] || pitches[i] < c->w) {
+            status[i] = ROI_EINVAL;
+            continue;
+        }
+        nxt[i] = 1 - c->cur;
+        uint8_t *base = c->buf + HDR_BYTES;
+        const void *fr[1] = {frames[i]};
+        const int sets[1] = {nxt[i]};
+        roi_status st = enqueue_expand(c->plan, base, 1, fr, pitches[i], c->dtype, &c->p, sets, ss[i],
+                                       phase_slot(c->buf, 0), c->primed ? c->cur : -1);
+        if (st != ROI_OK) return st;
+        if (!c->primed) {
+            c->primed = 1;
+            c->cur = nxt[i];
+            status[i] = ROI_PRIMED;
+            continue;
+        }
+        if (!flows[i]) {
+            status[i] = ROI_EINVAL;
+            continue;
+        }
+        enqueue_init_flow(c->plan, base, c->h, c->w, &c->p, flows[i], ss[i]);
         LAUNCH_CHECK();
-        c->hist_pos = (c->hist_pos + 1) % K;
-        if (c->hist_count < K) c->hist_count += 1;
+        jobs.push_back(i);
+    }
+    if (!jobs.empty()) {
+        // distinct streams of the jobs other than js
+        std::vector<hipStream_t> us;
+        for (int i : jobs)
+            if (ss[i] != js && std::find(us.begin(), us.end(), ss[i]) == us.end()) us.push_back(ss[i]);
+        if ((int)us.size() > SRV_FORK_MAX) return ROI_EINVAL;
+        for (size_t k = 0; k < us.size(); ++k) {
+            hipEventRecord(evs[k], us[k]);
+            hipStreamWaitEvent(js, evs[k], 0);
+        }
+        const roi_params *p = &cs[jobs[0]]->p;
+        const bool fp16 = cs[jobs[0]]->plan.fp16;
+        for (int l = p->levels - 1; l >= 1; --l) {
+            for (int it = 0; it < p->iterations; ++it) {
+                std::vector<IterArgs> as;
+                for (int i : jobs) {
+                    roi_stream_ctx *c = cs[i];
+                    as.push_back(make_iter_args(c->plan, c->buf + HDR_BYTES, (SelState *)c->buf, c->cur, nxt[i], c->w,
+                                                &c->p, flows[i], masks[i], l, it));
+                }
+                roi_status st = launch_iter_multi(as, fp16, js);
+                if (st != ROI_OK) return st;
+            }
+        }
+        for (size_t k = 0; k < us.size(); ++k) {
+            hipEventRecord(evs[SRV_FORK_MAX + k], js);
+            hipStreamWaitEvent(us[k], evs[SRV_FORK_MAX + k], 0);
+        }
+    }
+    for (int i : jobs) {
+        roi_stream_ctx *c = cs[i];
+        uint8_t *base = c->buf + HDR_BYTES;
+        for (int it = 0; it < c->p.iterations; ++it) {
+            roi_status st = launch_iter(make_iter_args(c->plan, base, (SelState *)c->buf, c->cur, nxt[i], c->w, &c->p,
+                                                       flows[i], masks[i], 0, it),
+                                        c->plan.fp16, ss[i], nullptr);
+            if (st != ROI_OK) return st;
+        }
+        if (masks[i]) {
+            roi_status st = enqueue_mask_stage(c->plan, base, (SelState *)c->buf, c->h, c->w, &c->p, masks[i], ss[i]);
+            if (st != ROI_OK) return st;
+        }
+        c->cur = nxt[i];
+        if (c->p.adjacent > 0 && masks[i]) {
+            roi_status st = enqueue_ensemble(c, masks[i], ss[i]);
+            if (st != ROI_OK) return st;
+        }
+        status[i] = ROI_OK;
     }
     return ROI_OK;
 }
@@ -1698,14 +1794,15 @@ roi_status roi_stream_push_many(int32_t n, void *const *ctxs, const void *const 
         if (c->dtype != ((roi_stream_ctx *)ctxs[0])->dtype ||
             std::memcmp(&c->p, &((roi_stream_ctx *)ctxs[0])->p, sizeof(roi_params)) != 0)
             return ROI_EINVAL;
+        for (int k = 0; k < i; ++k)
+            if (ctxs[k] == ctxs[i]) return ROI_EINVAL; // one frame per context per call
     }
     hipStream_t s = (hipStream_t)stream;
-    for (int i = 0; i < n; ++i) {
-        roi_status st = stream_push_one((roi_stream_ctx *)ctxs[i], frames[i], pitches[i], flows[i], masks[i], s);
-        if (st < 0) return st;
-        status[i] = st;
-    }
-    return ROI_OK;
+    std::vector<roi_stream_ctx *> cs(n);
+    std::vector<hipStream_t> ss(n, s);
+    for (int i = 0; i < n; ++i) cs[i] = (roi_stream_ctx *)ctxs[i];
+    hipEvent_t evs[2 * SRV_FORK_MAX] = {}; // unused: every context runs on s
+    return stream_push_batch(n, cs.data(), frames, pitches, flows, masks, status, ss.data(), s, evs);
 }
 
 // ---------------------------------------------------------------- timing

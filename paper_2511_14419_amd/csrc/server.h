@@ -46,6 +46,7 @@ struct SrvStep {
     std::vector<SrvFrame> frames;
     std::vector<int32_t> status;
     std::vector<hipEvent_t> done; // one per compute stream used
+    std::vector<hipEvent_t> aux;  // fork/join events of the step's shared grids
 };
 
 constexpr int SRV_COMPUTE_STREAMS = 4;
@@ -58,6 +59,7 @@ struct Server {
     hipStream_t copy_s = nullptr;
     hipStream_t comp_s[SRV_COMPUTE_STREAMS] = {};
     std::vector<hipEvent_t> ev_pool;
+    std::mutex ev_mu; // guards ev_pool (issue() runs without mu)
     std::mutex mu;
     std::condition_variable cv_sched, cv_done, cv_drain;
     std::deque<SrvStep *> inflight;
@@ -70,6 +72,7 @@ struct Server {
 
     hipEvent_t get_event()
     {
+        std::lock_guard<std::mutex> g(ev_mu);
         if (!ev_pool.empty()) {
             hipEvent_t e = ev_pool.back();
             ev_pool.pop_back();
@@ -121,9 +124,10 @@ struct Server {
         }
     }
 
-    // Copies the step's frames to their device slots and runs each stream's
-    // push on its compute stream; records one completion event per compute
-    // stream used.
+    // Copies the step's frames to their device slots and runs the step's
+    // pushes: each stream's own work on its compute stream, the coarse-level
+    // updates of all of them in shared grids on compute stream 0; records one
+    // completion event per compute stream used.
     void issue(SrvStep &st)
     {
         const size_t es = dtype_bytes(cfg.dtype);
@@ -146,11 +150,37 @@ struct Server {
         for (int i = 0; i < n; ++i) used_cs[streams[st.ids[i]].cstream] = true;
         for (int k = 0; k < SRV_COMPUTE_STREAMS; ++k)
             if (used_cs[k]) hipStreamWaitEvent(comp_s[k], copied, 0);
-        for (int i = 0; i < n; ++i) {
-            if (st.status[i] != ROI_OK) continue;
-            SrvStream &s = streams[st.ids[i]];
-            const SrvFrame &f = st.frames[i];
-            st.status[i] = stream_push_one(s.ctx, dev[i], cfg.w, f.flow, f.mask, comp_s[s.cstream]);
+        {
+            std::vector<int> idx;
+            std::vector<roi_stream_ctx *> cs;
+            std::vector<const void *> fr;
+            std::vector<int64_t> pitch;
+            std::vector<float *> fl;
+            std::vector<uint8_t *> mk;
+            std::vector<hipStream_t> ss;
+            for (int i = 0; i < n; ++i) {
+                if (st.status[i] != ROI_OK) continue;
+                SrvStream &s = streams[st.ids[i]];
+                idx.push_back(i);
+                cs.push_back(s.ctx);
+                fr.push_back(dev[i]);
+                pitch.push_back(cfg.w);
+                fl.push_back(st.frames[i].flow);
+                mk.push_back(st.frames[i].mask);
+                ss.push_back(comp_s[s.cstream]);
+            }
+            if (!idx.empty()) {
+                hipEvent_t evs[2 * SRV_FORK_MAX];
+                for (hipEvent_t &e : evs) {
+                    e = get_event();
+                    st.aux.push_back(e);
+                }
+                std::vector<int32_t> sub(idx.size(), ROI_OK);
+                const roi_status r = stream_push_batch((int)idx.size(), cs.data(), fr.data(), pitch.data(), fl.data(),
+                                                       mk.data(), sub.data(), ss.data(), comp_s[0], evs);
+                for (size_t k = 0; k < idx.size(); ++k) st.status[idx[k]] = r != ROI_OK ? r : sub[k];
+                used_cs[0] = true; // the shared grids ran there
+            }
         }
         for (int k = 0; k < SRV_COMPUTE_STREAMS; ++k) {
             if (!used_cs[k]) continue;
@@ -190,7 +220,11 @@ struct Server {
                 if (r.status < 0 && error == ROI_OK) error = (roi_status)r.status;
                 completed += 1;
             }
-            for (hipEvent_t e : st->done) ev_pool.push_back(e);
+            {
+                std::lock_guard<std::mutex> g(ev_mu);
+                for (hipEvent_t e : st->done) ev_pool.push_back(e);
+                for (hipEvent_t e : st->aux) ev_pool.push_back(e);
+            }
             delete st;
             cv_sched.notify_one();
             cv_drain.notify_all();

@@ -437,6 +437,40 @@ def test_push_many_matches_single_streams():
         s.close()
 
 
+def test_push_many_mixed_batch_and_duplicates():
+    """A batch that mixes a context's first frame (primed) with contexts that
+    produce flows, 18 contexts (two shared grids), the adjacent-frame
+    ensemble: each result equals the single-stream push; the same context
+    twice in one call is rejected."""
+    dev = device()
+    fl = F()
+    p = fl.default_params(adjacent=1)
+    sizes = [(96 + 8 * (i % 5), 100 + 12 * (i % 4)) for i in range(18)]
+    seqs = [synth.sequence_u16(h, w, 3, 3, 300 + i) for i, (h, w) in enumerate(sizes)]
+    frames = [[to_dev(f, dev) for f in s] for s in seqs]
+    many = [fl.Stream(h, w, fl.ROI_U16, p) for h, w in sizes]
+    one = [fl.Stream(h, w, fl.ROI_U16, p) for h, w in sizes]
+    flows = [torch.empty((h, w, 2), device=dev) for h, w in sizes]
+    masks = [torch.empty((h, w), dtype=torch.uint8, device=dev) for h, w in sizes]
+    f1 = [torch.empty((h, w, 2), device=dev) for h, w in sizes]
+    m1 = [torch.empty((h, w), dtype=torch.uint8, device=dev) for h, w in sizes]
+    # odd contexts start one step late: the second call mixes primed and flow
+    for t in range(3):
+        ids = [i for i in range(18) if i % 2 == 0 or t >= 1]
+        fr = [frames[i][t - (i % 2)] for i in ids]
+        st = fl.push_many([many[i] for i in ids], fr, [flows[i] for i in ids], [masks[i] for i in ids])
+        for k, i in enumerate(ids):
+            s1 = one[i].push(fr[k], f1[i], m1[i])
+            torch.cuda.synchronize()
+            assert st[k] == s1, (t, i)
+            if s1 == fl.ROI_OK:
+                assert torch.equal(flows[i], f1[i]) and torch.equal(masks[i], m1[i]), (t, i)
+    with pytest.raises(fl.RoiError):
+        fl.push_many([many[0], many[0]], [frames[0][0], frames[0][1]], [flows[0], flows[0]], [masks[0], masks[0]])
+    for s in many + one:
+        s.close()
+
+
 def test_fp16_storage_error_reported():
     """FP16 storage of the per-level expansions: the error against the FP64
     oracle is reported; the asserted bounds are loose (the variant trades
