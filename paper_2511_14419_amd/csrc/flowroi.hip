@@ -1473,12 +1473,17 @@ roi_status roi_mask_batched(int32_t n, const roi_pair *pairs, roi_dtype dtype, c
         hipStream_t cs = ds->cap;
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return ROI_EDEVICE;
         roi_status st = ROI_OK;
-        // fork: every auxiliary stream waits on the capture origin, pairs are
-        // spread over them so the graph holds independent per-pair chains
-        // 1. per pair on the auxiliary streams: pyramid and expansions (with
-        //    denoising / stabilisation) and the initial flow
+        // event ev recorded on `from`, waited for by `to` (a graph edge)
+        auto link = [&](hipEvent_t ev, hipStream_t from, hipStream_t to) {
+            if (hipEventRecord(ev, from) != hipSuccess || hipStreamWaitEvent(to, ev, 0) != hipSuccess)
+                st = ROI_EDEVICE;
+        };
+        // 1. per pair on the auxiliary streams (pairs spread over them):
+        //    pyramid and expansions (with denoising / stabilisation) and the
+        //    initial flow
         hipEventRecord(ds->ev[0], cs);
-        for (int k = 0; k < naux; ++k) hipStreamWaitEvent(ds->aux[k], ds->ev[0], 0);
+        for (int k = 0; k < naux; ++k)
+            if (hipStreamWaitEvent(ds->aux[k], ds->ev[0], 0) != hipSuccess) st = ROI_EDEVICE;
         struct Job {
             Plan pl;
             uint8_t *base;
@@ -1494,14 +1499,14 @@ roi_status roi_mask_batched(int32_t n, const roi_pair *pairs, roi_dtype dtype, c
             const int sets[2] = {0, 1};
             hipStream_t as = ds->aux[i % naux];
             st = enqueue_expand(pl, base, 2, frames, q.pitch, dtype, p, sets, as, phase_slot(ws, i));
-            if (st == ROI_OK) enqueue_init_flow(pl, base, q.h, q.w, p, q.flow, as);
+            if (st == ROI_OK) {
+                enqueue_init_flow(pl, base, q.h, q.w, p, q.flow, as);
+                if (hipGetLastError() != hipSuccess) st = ROI_EDEVICE;
+            }
             jobs.push_back({pl, base, i});
             base += pl.bytes;
         }
-        for (int k = 0; k < naux; ++k) {
-            hipEventRecord(ds->ev[k + 1], ds->aux[k]);
-            hipStreamWaitEvent(cs, ds->ev[k + 1], 0);
-        }
+        for (int k = 0; k < naux; ++k) link(ds->ev[k + 1], ds->aux[k], cs);
         // 2. every coarse level and update of all pairs in one grid (per
         //    IT_MULTI pairs): the coarse levels of many pairs fill the chip
         //    together
@@ -1519,8 +1524,9 @@ roi_status roi_mask_batched(int32_t n, const roi_pair *pairs, roi_dtype dtype, c
         }
         // 3. per pair on the auxiliary streams: the full-resolution updates
         //    (each fills the chip alone), threshold and dilation
-        hipEventRecord(ds->ev[naux + 1], cs);
-        for (int k = 0; k < naux; ++k) hipStreamWaitEvent(ds->aux[k], ds->ev[naux + 1], 0);
+        if (hipEventRecord(ds->ev[naux + 1], cs) != hipSuccess) st = ROI_EDEVICE;
+        for (int k = 0; k < naux; ++k)
+            if (hipStreamWaitEvent(ds->aux[k], ds->ev[naux + 1], 0) != hipSuccess) st = ROI_EDEVICE;
         for (const Job &jb : jobs) {
             if (st != ROI_OK) break;
             const roi_pair &q = pairs[jb.i];
@@ -1531,10 +1537,7 @@ roi_status roi_mask_batched(int32_t n, const roi_pair *pairs, roi_dtype dtype, c
             if (st == ROI_OK)
                 st = enqueue_mask_stage(jb.pl, jb.base, (SelState *)ws + jb.i, q.h, q.w, p, q.mask, as);
         }
-        for (int k = 0; k < naux; ++k) {
-            hipEventRecord(ds->ev[naux + 2 + k], ds->aux[k]);
-            hipStreamWaitEvent(cs, ds->ev[naux + 2 + k], 0);
-        }
+        for (int k = 0; k < naux; ++k) link(ds->ev[naux + 2 + k], ds->aux[k], cs);
         hipGraph_t graph = nullptr;
         const hipError_t ce = hipStreamEndCapture(cs, &graph);
         if (st != ROI_OK || ce != hipSuccess) {
@@ -1721,10 +1724,9 @@ static roi_status stream_push_batch(int n, roi_stream_ctx *const *cs, const void
         for (int i : jobs)
             if (ss[i] != js && std::find(us.begin(), us.end(), ss[i]) == us.end()) us.push_back(ss[i]);
         if ((int)us.size() > SRV_FORK_MAX) return ROI_EINVAL;
-        for (size_t k = 0; k < us.size(); ++k) {
-            hipEventRecord(evs[k], us[k]);
-            hipStreamWaitEvent(js, evs[k], 0);
-        }
+        for (size_t k = 0; k < us.size(); ++k)
+            if (hipEventRecord(evs[k], us[k]) != hipSuccess || hipStreamWaitEvent(js, evs[k], 0) != hipSuccess)
+                return ROI_EDEVICE;
         const roi_params *p = &cs[jobs[0]]->p;
         const bool fp16 = cs[jobs[0]]->plan.fp16;
         for (int l = p->levels - 1; l >= 1; --l) {
@@ -1739,10 +1741,10 @@ static roi_status stream_push_batch(int n, roi_stream_ctx *const *cs, const void
                 if (st != ROI_OK) return st;
             }
         }
-        for (size_t k = 0; k < us.size(); ++k) {
-            hipEventRecord(evs[SRV_FORK_MAX + k], js);
-            hipStreamWaitEvent(us[k], evs[SRV_FORK_MAX + k], 0);
-        }
+        for (size_t k = 0; k < us.size(); ++k)
+            if (hipEventRecord(evs[SRV_FORK_MAX + k], js) != hipSuccess ||
+                hipStreamWaitEvent(us[k], evs[SRV_FORK_MAX + k], 0) != hipSuccess)
+                return ROI_EDEVICE;
     }
     for (int i : jobs) {
         roi_stream_ctx *c = cs[i];
