@@ -70,6 +70,11 @@ __device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t off)
 {
     return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, 0);
+}
 __device__ __forceinline__ float bload1(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
@@ -557,7 +562,7 @@ __device__ __forceinline__ float bilerp(float p00, float p01, float p10, float p
 
 // Buffer descriptors of one launch (uniform across the grid).
 struct IterRes {
-    __amdgpu_buffer_rsrc_t p4a, p1a, p4b, p1b, fin;
+    __amdgpu_buffer_rsrc_t p4a, p1a, p4b, p1b, fin, fout;
 };
 
 // Loads that need nothing but the pixel position: prev's coefficients at x
@@ -883,7 +888,7 @@ __device__ __forceinline__ void iter_chunk(const IterArgs &a, const IterRes &rs,
             const float *vv = vsb + i * IT_TW + cc2;
             const float2 d = solve2(vv[0], vv[IT_CH * IT_TW], vv[2 * IT_CH * IT_TW], vv[3 * IT_CH * IT_TW],
                                     vv[4 * IT_CH * IT_TW], a.eps);
-            a.fout[(size_t)oy * a.fout_pitch + x] = d;
+            bstore2(rs.fout, ((uint32_t)oy * a.fout_pitch + x) * 8u, d);
             if (a.m2) a.m2[(size_t)oy * a.m2_pitch + x] = mag2(d);
             if (a.pre8) a.pre8[(size_t)oy * a.w + x] = __float_as_uint(mag2(d)) > a.t2bits ? 1 : 0;
         }
@@ -924,6 +929,7 @@ __device__ __forceinline__ void iter_tile(const IterArgs &a, int32_t strip, int3
     rs.p1b = make_rsrc(a.p1[1], npx * Packed<TS>::B1);
     rs.fin = make_rsrc(a.fin, PRIOR == PRIOR_UPSAMPLE ? (uint32_t)a.hc * a.fin_pitch * 8u
                                                       : (uint32_t)a.h * a.fin_pitch * 8u);
+    rs.fout = make_rsrc(a.fout, (uint32_t)a.h * a.fout_pitch * 8u);
     // step-1 pixels of this thread (the same slots in every chunk)
     IterSlots<R> sl;
 #pragma unroll
