@@ -2021,13 +2021,45 @@ __global__ __launch_bounds__(256) void k_fft_rows(float2 *data, int32_t P, const
     const int buf = fpad(P); // padded buffer length
     // the twiddle table staged once per block after the two row buffers
     float2 *tws = fsm + 2 * buf;
-    for (int i = threadIdx.x; i < P; i += 256) tws[i] = tw[i];
-    __syncthreads();
-    tw = tws;
     const float2 *src = row;
     bool src_lds = false;
     int Ns = 1;
-    for (int st = 0; st < steps; ++st) {
+    int st0 = 0;
+    if (n8 > 0 && P / 8 <= 256 && steps > 1) {
+        // the first radix-8 step needs no twiddles (Ns = 1): its row loads and
+        // the table's loads go out together, and one barrier serves both
+        constexpr int TWR = PH_MAXP / 256;
+        float2 twv[TWR];
+#pragma unroll
+        for (int k = 0; k < TWR; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
+            if (i < P) twv[k] = tw[i];
+        }
+        const int j = threadIdx.x;
+        if (j < P / 8) {
+            float2 v[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) v[r] = row[j + r * (P / 8)];
+            dft_small<INV, 8>(v);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) fsm[fpad(j * 8 + r)] = v[r];
+        }
+#pragma unroll
+        for (int k = 0; k < TWR; ++k) {
+            const int i = (int)threadIdx.x + 256 * k;
+            if (i < P) tws[i] = twv[k];
+        }
+        __syncthreads();
+        src = fsm;
+        src_lds = true;
+        Ns = 8;
+        st0 = 1;
+    } else {
+        for (int i = threadIdx.x; i < P; i += 256) tws[i] = tw[i];
+        __syncthreads();
+    }
+    tw = tws;
+    for (int st = st0; st < steps; ++st) {
         const bool last = st == steps - 1;
         float2 *dst = fsm + (st & 1) * buf;
         bool dst_lds = true;
