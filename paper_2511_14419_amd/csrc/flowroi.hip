@@ -338,18 +338,19 @@ struct PhaseIO {
     float *copy_out;
 };
 
+// The first forward row pass, packing the two frames as it reads them.
 template <typename TA, typename TB>
-void launch_pack2(const PhArgs &g, dim3 ge, hipStream_t s)
+void launch_pack2(const PhArgs &g, const float2 *tw, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_ph_pack<TA, TB>), ge, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_fft_rows_pack<TA, TB>), dim3(g.P), dim3(256), lds, s, g, tw);
 }
 
 template <typename TA>
-void launch_pack(roi_dtype db, const PhArgs &g, dim3 ge, hipStream_t s)
+void launch_pack(roi_dtype db, const PhArgs &g, const float2 *tw, size_t lds, hipStream_t s)
 {
-    if (db == ROI_U8) launch_pack2<TA, uint8_t>(g, ge, s);
-    else if (db == ROI_U16) launch_pack2<TA, uint16_t>(g, ge, s);
-    else launch_pack2<TA, float>(g, ge, s);
+    if (db == ROI_U8) launch_pack2<TA, uint8_t>(g, tw, lds, s);
+    else if (db == ROI_U16) launch_pack2<TA, uint16_t>(g, tw, lds, s);
+    else launch_pack2<TA, float>(g, tw, lds, s);
 }
 
 template <typename TS>
@@ -379,19 +380,18 @@ roi_status enqueue_phase(const PhaseBufs &b, const PhaseIO &io, int h, int w, Ph
         g.P = P;
         g.hann = b.hann;
         g.z = b.z;
-        const dim3 ge((P + 63) / 64, (P + 3) / 4), gt((P + 31) / 32, (P + 31) / 32);
+        const dim3 gt((P + 31) / 32, (P + 31) / 32);
         const size_t lds = (2 * (size_t)(P + P / 16) + P) * sizeof(float2); // two padded row buffers + twiddles
-        if (io.dref == ROI_U8) launch_pack<uint8_t>(io.dmov, g, ge, s);
-        else if (io.dref == ROI_U16) launch_pack<uint16_t>(io.dmov, g, ge, s);
-        else launch_pack<float>(io.dmov, g, ge, s);
-        hipLaunchKernelGGL((k_fft_rows<false, false>), dim3(P), dim3(256), lds, s, b.z, P, (const float2 *)b.tw,
-                           (float *)nullptr, (unsigned long long *)nullptr);
+        const float2 *tw = (const float2 *)b.tw;
+        // z = window (a + i b) packed on the fly, rows, transpose, rows: Z^T
+        if (io.dref == ROI_U8) launch_pack<uint8_t>(io.dmov, g, tw, lds, s);
+        else if (io.dref == ROI_U16) launch_pack<uint16_t>(io.dmov, g, tw, lds, s);
+        else launch_pack<float>(io.dmov, g, tw, lds, s);
         hipLaunchKernelGGL(k_transpose, gt, dim3(256), 0, s, (const float2 *)b.z, b.t, P);
-        hipLaunchKernelGGL((k_fft_rows<false, false>), dim3(P), dim3(256), lds, s, b.t, P, (const float2 *)b.tw,
-                           (float *)nullptr, (unsigned long long *)nullptr);
-        hipLaunchKernelGGL(k_ph_cross, ge, dim3(256), 0, s, (const float2 *)b.t, b.z, P);
-        hipLaunchKernelGGL((k_fft_rows<true, false>), dim3(P), dim3(256), lds, s, b.z, P, (const float2 *)b.tw,
-                           (float *)nullptr, (unsigned long long *)nullptr);
+        hipLaunchKernelGGL((k_fft_rows<false, false>), dim3(P), dim3(256), lds, s, b.t, P, tw, (float *)nullptr,
+                           (unsigned long long *)nullptr);
+        // cross power made on the fly, inverse rows, transpose, inverse rows
+        hipLaunchKernelGGL(k_fft_rows_cross, dim3(P), dim3(256), lds, s, (const float2 *)b.t, b.z, P, tw);
         hipLaunchKernelGGL(k_transpose, gt, dim3(256), 0, s, (const float2 *)b.z, b.t, P);
         hipLaunchKernelGGL((k_fft_rows<true, true>), dim3(P), dim3(256), lds, s, b.t, P, (const float2 *)b.tw, surface,
                            b.keys);

@@ -1895,19 +1895,6 @@ struct PhArgs {
     float2 *z;                                   // P x P
 };
 
-// z = hann(y) hann(x) (a + i b) over the window, frames read in their own
-// element types. grid: (ceil(P/64), ceil(P/4))
-template <typename TA, typename TB>
-__global__ __launch_bounds__(256) void k_ph_pack(PhArgs g)
-{
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (x >= g.P || y >= g.P) return;
-    const float va = (float)((const TA *)g.a)[(size_t)(g.y0 + y) * g.pitch_a + g.x0 + x];
-    const float vb = (float)((const TB *)g.b)[(size_t)(g.y0 + y) * g.pitch_b + g.x0 + x];
-    const float wgt = g.hann[y] * g.hann[x];
-    g.z[(size_t)y * g.P + x] = make_float2(wgt * va, wgt * vb);
-}
-
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
@@ -2002,19 +1989,68 @@ __device__ __forceinline__ void fft_step(const float2 *src, bool src_lds, float2
     }
 }
 
+// Where the first step of fft_row takes element x of its row from. ROW: a
+// row of a P x P field in global memory, transformed in place.
+struct RowSrc {
+    static constexpr bool ROW = true;
+    const float2 *row;
+    __device__ float2 operator()(int x) const { return row[x]; }
+};
+
+// Row y of the packed windowed pair z = hann(y) hann(x) (a + i b), the
+// frames read in their own element types: the registration's input, made
+// on the fly by the first forward pass.
+template <typename TA, typename TB> struct PackSrc {
+    static constexpr bool ROW = false;
+    PhArgs g;
+    int y;
+    __device__ float2 operator()(int x) const
+    {
+        const float va = (float)((const TA *)g.a)[(size_t)(g.y0 + y) * g.pitch_a + g.x0 + x];
+        const float vb = (float)((const TB *)g.b)[(size_t)(g.y0 + y) * g.pitch_b + g.x0 + x];
+        const float wgt = g.hann[y] * g.hann[x];
+        return make_float2(wgt * va, wgt * vb);
+    }
+};
+
+// Row q of the normalised cross power spectrum, made on the fly by the first
+// inverse pass from the transposed spectrum zt of z = a + i b: with Z(k) and
+// M = Z(-k), A = Z + conj(M) = 2 F_a, B = -i (Z - conj(M)) = 2 F_b and
+// R = B conj(A) / (|A| |B|) (0 where either vanishes), so the correlation
+// peak sits at the shift of b against a.
+struct CrossSrc {
+    static constexpr bool ROW = false;
+    const float2 *zt;
+    int q, P;
+    __device__ float2 operator()(int x) const
+    {
+        const float2 Z = zt[(size_t)q * P + x];
+        const float2 M = zt[(size_t)((P - q) & (P - 1)) * P + ((P - x) & (P - 1))];
+        const float2 A = make_float2(Z.x + M.x, Z.y - M.y); // Z + conj(M)
+        const float2 D = make_float2(Z.x - M.x, Z.y + M.y); // Z - conj(M)
+        const float2 B = make_float2(D.y, -D.x);            // -i D
+        const float na = __fmaf_rn(A.x, A.x, A.y * A.y), nb = __fmaf_rn(B.x, B.x, B.y * B.y);
+        float2 r = make_float2(0.0f, 0.0f);
+        if (na > 0.0f && nb > 0.0f) {
+            const float sc = rsqrtf(na) * rsqrtf(nb);
+            r = make_float2((B.x * A.x + B.y * A.y) * sc, (B.y * A.x - B.x * A.y) * sc);
+        }
+        return r;
+    }
+};
+
 // One Stockham FFT per row of a P x P complex field (P a power of two):
 // radix-8 steps then one radix-4 or radix-2 step, each step a pass through
-// LDS (two P-point buffers), the first reading the row from global memory
-// and the last writing it back. INV: inverse with 1/P. LAST (inverse only):
+// LDS (two P-point buffers), the first reading its input through `in` (see
+// RowSrc) and the last writing the row to `row`. INV: inverse with 1/P. LAST (inverse only):
 // instead of storing the row, the real parts go to `surface` (nullable) and
 // into the argmax keys. grid: P blocks, 256 threads, 2 fpad(P) + P float2
 // of dynamic LDS (two row buffers and the twiddle table)
-template <bool INV, bool LAST>
-__global__ __launch_bounds__(256) void k_fft_rows(float2 *data, int32_t P, const float2 *tw, float *surface,
-                                                  unsigned long long *keys)
+template <bool INV, bool LAST, typename Src>
+__device__ __forceinline__ void fft_row(const Src &in, float2 *row, int32_t P, const float2 *tw, float *surface,
+                                        unsigned long long *keys)
 {
     extern __shared__ float2 fsm[];
-    float2 *row = data + (size_t)blockIdx.x * P;
     const int lg = __ffs(P) - 1, n8 = lg / 3, rem = lg % 3;
     const int steps = n8 + (rem ? 1 : 0);
     const float sc = INV ? 1.0f / (float)P : 1.0f;
@@ -2039,7 +2075,7 @@ __global__ __launch_bounds__(256) void k_fft_rows(float2 *data, int32_t P, const
         if (j < P / 8) {
             float2 v[8];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) v[r] = row[j + r * (P / 8)];
+            for (int r = 0; r < 8; ++r) v[r] = in(j + r * (P / 8));
             dft_small<INV, 8>(v);
 #pragma unroll
             for (int r = 0; r < 8; ++r) fsm[fpad(j * 8 + r)] = v[r];
@@ -2056,6 +2092,12 @@ __global__ __launch_bounds__(256) void k_fft_rows(float2 *data, int32_t P, const
         st0 = 1;
     } else {
         for (int i = threadIdx.x; i < P; i += 256) tws[i] = tw[i];
+        if (!Src::ROW) {
+            // the second row buffer holds the made row; step 0 writes the first
+            for (int i = threadIdx.x; i < P; i += 256) fsm[buf + fpad(i)] = in(i);
+            src = fsm + buf;
+            src_lds = true;
+        }
         __syncthreads();
     }
     tw = tws;
@@ -2107,6 +2149,31 @@ __global__ __launch_bounds__(256) void k_fft_rows(float2 *data, int32_t P, const
     }
 }
 
+template <bool INV, bool LAST>
+__global__ __launch_bounds__(256) void k_fft_rows(float2 *data, int32_t P, const float2 *tw, float *surface,
+                                                  unsigned long long *keys)
+{
+    float2 *row = data + (size_t)blockIdx.x * P;
+    fft_row<INV, LAST>(RowSrc{row}, row, P, tw, surface, keys);
+}
+
+// The first forward pass over rows, its input packed from the two frames on
+// the fly (PackSrc); output rows to g.z. grid: P blocks, as k_fft_rows
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_fft_rows_pack(PhArgs g, const float2 *tw)
+{
+    fft_row<false, false>(PackSrc<TA, TB>{g, (int)blockIdx.x}, g.z + (size_t)blockIdx.x * g.P, g.P, tw, nullptr,
+                          nullptr);
+}
+
+// The first inverse pass over rows, its input the cross power made on the
+// fly from the transposed spectrum zt (CrossSrc); output rows to rt.
+// grid: P blocks, as k_fft_rows
+__global__ __launch_bounds__(256) void k_fft_rows_cross(const float2 *zt, float2 *rt, int32_t P, const float2 *tw)
+{
+    fft_row<true, false>(CrossSrc{zt, (int)blockIdx.x, P}, rt + (size_t)blockIdx.x * P, P, tw, nullptr, nullptr);
+}
+
 // out = in^T for P x P complex fields, 32 x 32 tiles through LDS.
 // grid: (ceil(P/32), ceil(P/32)), 256 threads
 __global__ __launch_bounds__(256) void k_transpose(const float2 *in, float2 *out, int32_t P)
@@ -2119,25 +2186,6 @@ __global__ __launch_bounds__(256) void k_transpose(const float2 *in, float2 *out
     __syncthreads();
     for (int k = 0; k < 32; k += 8)
         if (bx + ty + k < P && by + tx < P) out[(size_t)(bx + ty + k) * P + by + tx] = t[tx][ty + k];
-}
-
-// R(k) = (B / |B|) conj(A / |A|) from the transposed spectrum of z. grid: (P/64, P/4)
-__global__ __launch_bounds__(256) void k_ph_cross(const float2 *zt, float2 *rt, int32_t P)
-{
-    const int ky = blockIdx.x * 64 + (threadIdx.x & 63), kx = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (ky >= P || kx >= P) return;
-    const float2 Z = zt[(size_t)kx * P + ky];
-    const float2 M = zt[(size_t)((P - kx) & (P - 1)) * P + ((P - ky) & (P - 1))];
-    const float2 A = make_float2(Z.x + M.x, Z.y - M.y);          // Z + conj(M)
-    const float2 D = make_float2(Z.x - M.x, Z.y + M.y);          // Z - conj(M)
-    const float2 B = make_float2(D.y, -D.x);                     // -i D
-    const float na = __fmaf_rn(A.x, A.x, A.y * A.y), nb = __fmaf_rn(B.x, B.x, B.y * B.y);
-    float2 r = make_float2(0.0f, 0.0f);
-    if (na > 0.0f && nb > 0.0f) {
-        const float s = rsqrtf(na) * rsqrtf(nb);
-        r = make_float2((B.x * A.x + B.y * A.y) * s, (B.y * A.x - B.x * A.y) * s); // B conj(A) / (|A| |B|)
-    }
-    rt[(size_t)kx * P + ky] = r;
 }
 
 struct ApplyArgs {
