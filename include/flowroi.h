@@ -388,6 +388,13 @@ void roi_timing_enable(int32_t mode);
 roi_status roi_timing_read(double *total_ms, int64_t *launches, int64_t *pixels, double *bytes);
 void roi_timing_reset(void);
 
+/* Mode 2 brackets only every `every`-th call (counted from the last
+ * roi_timing_reset; values below 1 mean 1, the default). Recording an event
+ * leaves the GPU idle for a few microseconds between the kernels around it,
+ * so sampling the calls keeps that cost out of a throughput measurement
+ * while the sampled calls still give the kernel's launch times. */
+void roi_timing_sample(int32_t every);
+
 /* Records behind roi_timing_read (same synchronisation): fills up to `max`
  * entries of kernel ms, output pixels and algorithmic bytes, one per launch
  * (mode 1) or per call (mode 2), in order, and returns the number of

@@ -154,9 +154,20 @@ struct TimedLaunch {
     int32_t n; // launches inside the bracket
 };
 
+// An event used only for its timestamp: no system-scope fence when it is
+// recorded (nothing reads memory through it), so the record does not write
+// back and invalidate the caches between the launches it brackets.
+static hipEvent_t timing_event()
+{
+    hipEvent_t e = nullptr;
+    return hipEventCreateWithFlags(&e, hipEventDisableSystemFence) == hipSuccess ? e : nullptr;
+}
+
 struct Timing {
     std::mutex mu;
     int mode = 0; // 0 off, 1 per launch, 2 per call
+    int every = 1;         // mode 2 brackets every `every`-th call
+    int64_t calls = 0;     // mode-2 calls seen since the last reset
     std::vector<TimedLaunch> pending;
     std::vector<hipEvent_t> pool;
     double done_ms = 0, done_bytes = 0;
@@ -171,8 +182,7 @@ struct Timing {
             pool.pop_back();
             return e;
         }
-        hipEvent_t e = nullptr;
-        return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+        return timing_event();
     }
 } g_timing;
 
@@ -639,7 +649,7 @@ int choose_strip(const IterArgs &a, bool fp16, hipStream_t s)
     constexpr int NE = 2 * N_STRIP_CANDIDATES;
     hipEvent_t e[NE];
     int n = 0;
-    while (n < NE && hipEventCreate(&e[n]) == hipSuccess) ++n;
+    while (n < NE && (e[n] = timing_event()) != nullptr) ++n;
     int best = heuristic_strip(a.h, a.w);
     if (n == NE) {
         float best_ms = 1e30f;
@@ -680,6 +690,7 @@ struct Bracket {
         {
             std::lock_guard<std::mutex> lk(g_timing.mu);
             if (g_timing.mode != mode || capturing(st)) return;
+            if (mode == 2 && g_timing.calls++ % g_timing.every != 0) return;
             e0 = g_timing.get();
             e1 = g_timing.get();
         }
@@ -1815,8 +1826,8 @@ void roi_timing_enable(int32_t mode)
     g_timing.mode = mode == 1 || mode == 2 ? mode : 0;
     // event creation is far slower than a record: fill the pool up front
     while (g_timing.mode && g_timing.pool.size() < ROI_TIMING_POOL) {
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) break;
+        hipEvent_t e = timing_event();
+        if (!e) break;
         g_timing.pool.push_back(e);
     }
 }
@@ -1846,6 +1857,12 @@ roi_status roi_timing_read(double *total_ms, int64_t *launches, int64_t *pixels,
     return ROI_OK;
 }
 
+void roi_timing_sample(int32_t every)
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.every = every > 1 ? every : 1;
+}
+
 void roi_timing_reset(void)
 {
     std::lock_guard<std::mutex> lk(g_timing.mu);
@@ -1855,6 +1872,7 @@ void roi_timing_reset(void)
         g_timing.pool.push_back(t.e1);
     }
     g_timing.pending.clear();
+    g_timing.calls = 0;
     g_timing.done_ms = 0;
     g_timing.done_bytes = 0;
     g_timing.done_n = 0;

@@ -29,7 +29,7 @@ EXPORTED = [
     "roi_phase_workspace_size", "roi_phase_correlation", "roi_stream_read_shift",
     "roi_pyr_down", "roi_poly_expand", "roi_denoise", "roi_batched_workspace_size", "roi_mask_batched",
     "roi_stream_create", "roi_stream_push", "roi_stream_reset", "roi_stream_state_bytes",
-    "roi_stream_destroy", "roi_stream_push_many", "roi_timing_enable", "roi_timing_read",
+    "roi_stream_destroy", "roi_stream_push_many", "roi_timing_enable", "roi_timing_read", "roi_timing_sample",
     "roi_timing_reset", "roi_timing_records", "roi_autotune", "roi_set_strip", "roi_tuned_strip", "roi_status_str",
     "roi_server_create", "roi_server_open_stream", "roi_server_close_stream", "roi_server_stream_bytes",
     "roi_server_submit", "roi_server_poll", "roi_server_drain", "roi_server_destroy",
@@ -135,6 +135,8 @@ def lib():
         L.roi_stream_push_many.restype = i32
         L.roi_timing_enable.argtypes = [i32]
         L.roi_timing_enable.restype = None
+        L.roi_timing_sample.argtypes = [i32]
+        L.roi_timing_sample.restype = None
         L.roi_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                       ctypes.POINTER(ctypes.c_double)]
         L.roi_timing_read.restype = i32
@@ -429,9 +431,10 @@ def push_many(streams, frames, flows, masks, stream=None):
     return list(st)
 
 
-def timing_enable(on=True, per_call=False):
+def timing_enable(on=True, per_call=False, every=1):
     """Iteration-kernel timing: off, per launch, or (per_call) one bracket
-    around each call's run of iteration launches."""
+    around each call's run of iteration launches, on every `every`-th call."""
+    lib().roi_timing_sample(every)
     lib().roi_timing_enable((2 if per_call else 1) if on else 0)
 
 
