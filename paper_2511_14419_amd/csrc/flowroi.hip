@@ -730,9 +730,12 @@ roi_status launch_iter(const IterArgs &a, bool fp16, hipStream_t s, Bracket *cal
 }
 
 // Several pairs' launches of one level and update, IT_MULTI pairs per grid
-// (k_iter_multi). One strip height per grid: the tallest candidate that
-// still gives >= 512 workgroups (2 per CU) over the group, since many pairs
-// together fill the chip with taller, cheaper strips.
+// (k_iter_multi). One strip height per grid: the tallest power of two up to
+// 128 rows that still gives >= 512 workgroups (2 per CU) over the group.
+// Taller strips would cut the halo re-reads further, but a workgroup walks
+// its strip as a chain of dependent chunks, and 256-row chains in the grid's
+// last partial round left most of the chip idle (16 lens streams: 4.4 ms
+// per batch with a 256-row cap, 4.25 ms with this one).
 int multi_strip(const IterArgs *as, int n)
 {
     auto wgs = [&](int st) {
@@ -740,7 +743,7 @@ int multi_strip(const IterArgs *as, int n)
         for (int i = 0; i < n; ++i) t += (long)((as[i].w + IT_TW - 1) / IT_TW) * ((as[i].h + st - 1) / st);
         return t;
     };
-    int strip = 256;
+    int strip = 128;
     while (strip > 8 && wgs(strip) < 512) strip /= 2;
     return strip;
 }
