@@ -24,9 +24,13 @@
  *     and runs asynchronously. Parameter errors are detected on the host
  *     before anything is enqueued; on any error status nothing was enqueued
  *     (except ROI_EDEVICE, which reports a failed launch).
- *   - No entry point allocates device memory except roi_stream_create.
- *     Scratch comes from a caller-provided workspace of at least
- *     roi_workspace_size() bytes, 256-byte aligned.
+ *   - No entry point allocates device memory except roi_stream_create and
+ *     roi_server_create (and roi_server_open_stream, inside the server's
+ *     HBM budget). Scratch comes from a caller-provided workspace of at
+ *     least roi_workspace_size() bytes, 256-byte aligned. roi_mask_batched
+ *     keeps its instantiated HIP graphs, and the batched path and the
+ *     server their own streams and events, until the process ends (or the
+ *     server is destroyed).
  *   - Calls that share a workspace or a stream context must not overlap.
  */
 #ifndef FLOWROI_H
@@ -91,14 +95,14 @@ typedef struct roi_params {
     int32_t levels;        /* pyramid levels, 1..10; level l+1 = binomial-blurred level l at even pixels */
     int32_t winsize;       /* side of the square pooling window, odd, 1..15 */
     int32_t iterations;    /* displacement updates per level, 1..64 */
-    int32_t poly_n;        /* expansion neighbourhood side, 5 or 7 */
+    int32_t poly_n;        /* expansion neighbourhood side, 3, 5 or 7 */
     float poly_sigma;      /* Gaussian applicability sigma (pixels), > 0 */
     float eps;             /* regulariser: den = max(det G, eps (tr G)^2), > 0 */
     int32_t thresh_mode;   /* ROI_THRESH_ABS or ROI_THRESH_TOP */
     float thresh;          /* ABS: pixels, >= 0; TOP: fraction in (0, 1) */
     int32_t dilate_radius; /* structuring-element radius, 0..32 */
     int32_t se_shape;      /* ROI_SE_SQUARE or ROI_SE_DISC */
-    uint32_t flags;        /* ROI_USE_INITIAL_FLOW | ROI_FP16_STORAGE */
+    uint32_t flags;        /* ROI_USE_INITIAL_FLOW | ROI_FP16_STORAGE | ROI_STABILIZE */
     /* Denoising pre-stage (Method, Optical flow extraction: median then
      * bilateral filtering; Table 1 "Denoise" on/off), applied to both
      * frames before the pyramid. */
@@ -254,9 +258,10 @@ size_t roi_batched_workspace_size(int32_t n, const roi_pair *pairs, roi_dtype dt
 
 /* All n pairs through the whole path. Each pair's result is the one roi_mask
  * gives for it alone (the same per-pixel arithmetic, bit for bit). The
- * expansions and the mask stages run as independent per-pair branches; each
- * level and update of the flow is one launch over up to 16 pairs at once,
- * so the coarse levels of many pairs fill the GPU together. The launch
+ * expansions, the full-resolution updates and the mask stages run as
+ * independent per-pair branches; each coarse-level update is one launch
+ * over up to 16 pairs at once, so the coarse levels of many pairs fill the
+ * GPU together. The launch
  * sequence for a given (pairs, dtype, params, ws) is captured into a HIP
  * graph on first use and replayed afterwards. n in 1..256. */
 roi_status roi_mask_batched(int32_t n, const roi_pair *pairs, roi_dtype dtype, const roi_params *p,
