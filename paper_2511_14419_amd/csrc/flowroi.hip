@@ -930,7 +930,8 @@ roi_status enqueue_mask(const MaskBufs &mb, SelState *slot, int h, int w, const 
     if (d.r <= DB_MAXR) {
         const dim3 g((w + DIL_TW - 1) / DIL_TW, (h + DB_TH - 1) / DB_TH);
         if (d.lab) hipLaunchKernelGGL(k_dilate_bits<2>, g, dim3(256), 0, s, d);
-        else if (d.pre8 && w % 8 == 0 && (uintptr_t)d.pre8 % 8 == 0)
+        else if (d.pre8 && w % 8 == 0 && (uintptr_t)d.pre8 % 8 == 0 && (uintptr_t)d.mask % 4 == 0 &&
+                 d.mask_pitch % 4 == 0)
             hipLaunchKernelGGL(k_dilate_wide, g, dim3(256), 0, s, d);
         else if (d.pre8) hipLaunchKernelGGL(k_dilate_bits<1>, g, dim3(256), 0, s, d);
         else hipLaunchKernelGGL(k_dilate_bits<0>, g, dim3(256), 0, s, d);

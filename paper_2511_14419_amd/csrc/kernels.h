@@ -1352,12 +1352,16 @@ __global__ __launch_bounds__(256) void k_dilate_wide(DilArgs a)
         out[tx] = (uint64_t)(m >> 16); // the tile's own 64 columns
     }
     __syncthreads();
-    const int x = blockIdx.x * DIL_TW + tx;
-    if (x >= a.w) return;
-    for (int yy = ty; yy < DB_TH; yy += 4) {
+    // 4 mask bytes per lane: 16 lanes per row, 16 rows per pass (w is a
+    // multiple of 8 and the mask rows 4-byte aligned on this path)
+    const int q = t & 15, x4 = blockIdx.x * DIL_TW + 4 * q;
+    if (x4 >= a.w) return;
+    for (int yy = t >> 4; yy < DB_TH; yy += 16) {
         const int y = blockIdx.y * DB_TH + yy;
         if (y >= a.h) break;
-        a.mask[(size_t)y * a.mask_pitch + x] = (uint8_t)((out[yy] >> tx) & 1);
+        const uint32_t b = (uint32_t)(out[yy] >> (4 * q)) & 15u;
+        *(uint32_t *)(a.mask + (size_t)y * a.mask_pitch + x4) =
+            (b & 1u) | ((b & 2u) << 7) | ((b & 4u) << 14) | ((b & 8u) << 21);
     }
 }
 
