@@ -18,7 +18,7 @@
 // (k_sal_max, k_sal: motion saliency from |d| and its gradient; k_open_close:
 // threshold, opening, closing and tile-local component labels; k_cc_border,
 // k_cc_compress, k_cc_keep: components across tiles, their areas, the kept
-// ones), phase-correlation stabilisation (k_ph_*, k_fft_rows, k_transpose)
+// ones), phase-correlation stabilisation (k_ph_*, k_fft_rows*, k_transpose)
 // and the adjacent-frame ensemble (k_ensemble) complete the set.
 //
 // Every kernel is a plain grid over output tiles staged through LDS. Pyramid
