@@ -390,21 +390,21 @@ roi_status enqueue_phase(const PhaseBufs &b, const PhaseIO &io, int h, int w, Ph
         g.P = P;
         g.hann = b.hann;
         g.z = b.z;
-        const dim3 gt((P + 31) / 32, (P + 31) / 32);
         const size_t lds = (2 * (size_t)(P + P / 16) + P) * sizeof(float2); // two padded row buffers + twiddles
         const float2 *tw = (const float2 *)b.tw;
-        // z = window (a + i b) packed on the fly, rows, transpose, rows: Z^T
+        // z = window (a + i b), packed on the fly and transformed along its
+        // rows; then along the columns into t = Z^T (transposed as it goes)
         if (io.dref == ROI_U8) launch_pack<uint8_t>(io.dmov, g, tw, lds, s);
         else if (io.dref == ROI_U16) launch_pack<uint16_t>(io.dmov, g, tw, lds, s);
         else launch_pack<float>(io.dmov, g, tw, lds, s);
-        hipLaunchKernelGGL(k_transpose, gt, dim3(256), 0, s, (const float2 *)b.z, b.t, P);
-        hipLaunchKernelGGL((k_fft_rows<false, false>), dim3(P), dim3(256), lds, s, b.t, P, tw, (float *)nullptr,
-                           (unsigned long long *)nullptr);
-        // cross power made on the fly, inverse rows, transpose, inverse rows
+        hipLaunchKernelGGL((k_fft_cols<false, false>), dim3(P), dim3(256), lds, s, (const float2 *)b.z, b.t, P, tw,
+                           (float *)nullptr, (unsigned long long *)nullptr);
+        // the cross power made on the fly from t and inverse-transformed
+        // along its rows into z; then inverse along the columns, the real
+        // parts to the surface and the argmax
         hipLaunchKernelGGL(k_fft_rows_cross, dim3(P), dim3(256), lds, s, (const float2 *)b.t, b.z, P, tw);
-        hipLaunchKernelGGL(k_transpose, gt, dim3(256), 0, s, (const float2 *)b.z, b.t, P);
-        hipLaunchKernelGGL((k_fft_rows<true, true>), dim3(P), dim3(256), lds, s, b.t, P, (const float2 *)b.tw, surface,
-                           b.keys);
+        hipLaunchKernelGGL((k_fft_cols<true, true>), dim3(P), dim3(256), lds, s, (const float2 *)b.z, b.t, P, tw,
+                           surface, b.keys);
     }
     ApplyArgs a{};
     a.src = io.mov;

@@ -18,7 +18,7 @@
 // (k_sal_max, k_sal: motion saliency from |d| and its gradient; k_open_close:
 // threshold, opening, closing and tile-local component labels; k_cc_border,
 // k_cc_compress, k_cc_keep: components across tiles, their areas, the kept
-// ones), phase-correlation stabilisation (k_ph_*, k_fft_rows*, k_transpose)
+// ones), phase-correlation stabilisation (k_ph_*, k_fft_*)
 // and the adjacent-frame ensemble (k_ensemble) complete the set.
 //
 // Every kernel is a plain grid over output tiles staged through LDS. Pyramid
@@ -1993,19 +1993,10 @@ __device__ __forceinline__ void fft_step(const float2 *src, bool src_lds, float2
     }
 }
 
-// Where the first step of fft_row takes element x of its row from. ROW: a
-// row of a P x P field in global memory, transformed in place.
-struct RowSrc {
-    static constexpr bool ROW = true;
-    const float2 *row;
-    __device__ float2 operator()(int x) const { return row[x]; }
-};
-
 // Row y of the packed windowed pair z = hann(y) hann(x) (a + i b), the
 // frames read in their own element types: the registration's input, made
 // on the fly by the first forward pass.
 template <typename TA, typename TB> struct PackSrc {
-    static constexpr bool ROW = false;
     PhArgs g;
     int y;
     __device__ float2 operator()(int x) const
@@ -2023,7 +2014,6 @@ template <typename TA, typename TB> struct PackSrc {
 // R = B conj(A) / (|A| |B|) (0 where either vanishes), so the correlation
 // peak sits at the shift of b against a.
 struct CrossSrc {
-    static constexpr bool ROW = false;
     const float2 *zt;
     int q, P;
     __device__ float2 operator()(int x) const
@@ -2045,14 +2035,16 @@ struct CrossSrc {
 
 // One Stockham FFT per row of a P x P complex field (P a power of two):
 // radix-8 steps then one radix-4 or radix-2 step, each step a pass through
-// LDS (two P-point buffers), the first reading its input through `in` (see
-// RowSrc) and the last writing the row to `row`. INV: inverse with 1/P. LAST (inverse only):
-// instead of storing the row, the real parts go to `surface` (nullable) and
-// into the argmax keys. grid: P blocks, 256 threads, 2 fpad(P) + P float2
-// of dynamic LDS (two row buffers and the twiddle table)
+// LDS (two P-point buffers), the first reading its input through `in`
+// (PackSrc, CrossSrc, ColSrc: element x of the row, made on the fly) and the
+// last writing the row to `row`; rid is the row's index in the field.
+// INV: inverse with 1/P. LAST (inverse only): instead of storing the row,
+// the real parts go to `surface` (nullable) and into the argmax keys.
+// grid: P blocks, 256 threads, 2 fpad(P) + P float2 of dynamic LDS (two row
+// buffers and the twiddle table)
 template <bool INV, bool LAST, typename Src>
 __device__ __forceinline__ void fft_row(const Src &in, float2 *row, int32_t P, const float2 *tw, float *surface,
-                                        unsigned long long *keys)
+                                        unsigned long long *keys, int rid)
 {
     extern __shared__ float2 fsm[];
     const int lg = __ffs(P) - 1, n8 = lg / 3, rem = lg % 3;
@@ -2096,12 +2088,10 @@ __device__ __forceinline__ void fft_row(const Src &in, float2 *row, int32_t P, c
         st0 = 1;
     } else {
         for (int i = threadIdx.x; i < P; i += 256) tws[i] = tw[i];
-        if (!Src::ROW) {
-            // the second row buffer holds the made row; step 0 writes the first
-            for (int i = threadIdx.x; i < P; i += 256) fsm[buf + fpad(i)] = in(i);
-            src = fsm + buf;
-            src_lds = true;
-        }
+        // the second row buffer holds the input row; step 0 writes the first
+        for (int i = threadIdx.x; i < P; i += 256) fsm[buf + fpad(i)] = in(i);
+        src = fsm + buf;
+        src_lds = true;
         __syncthreads();
     }
     tw = tws;
@@ -2132,10 +2122,10 @@ __device__ __forceinline__ void fft_row(const Src &in, float2 *row, int32_t P, c
     unsigned long long best = 0ull;
     for (int i = threadIdx.x; i < P; i += 256) {
         const float v = src[src_lds ? fpad(i) : i].x;
-        if (surface) surface[(size_t)blockIdx.x * P + i] = v;
+        if (surface) surface[(size_t)rid * P + i] = v;
         const uint32_t b = __float_as_uint(v);
         const uint32_t ord = (b & 0x80000000u) ? ~b : (b | 0x80000000u); // orders like the float
-        const uint32_t idx = (uint32_t)(blockIdx.x * P + i);
+        const uint32_t idx = (uint32_t)(rid * P + i);
         const unsigned long long key = ((unsigned long long)ord << 32) | (0xFFFFFFFFu - idx);
         best = key > best ? key : best;
     }
@@ -2149,47 +2139,46 @@ __device__ __forceinline__ void fft_row(const Src &in, float2 *row, int32_t P, c
     if (threadIdx.x == 0) {
         unsigned long long m = red[0];
         for (int k = 1; k < 4; ++k) m = red[k] > m ? red[k] : m;
-        atomicMax(keys + (blockIdx.x % PH_SLOTS) * PH_SLOT_STRIDE, m);
+        atomicMax(keys + (rid % PH_SLOTS) * PH_SLOT_STRIDE, m);
     }
 }
 
-template <bool INV, bool LAST>
-__global__ __launch_bounds__(256) void k_fft_rows(float2 *data, int32_t P, const float2 *tw, float *surface,
-                                                  unsigned long long *keys)
-{
-    float2 *row = data + (size_t)blockIdx.x * P;
-    fft_row<INV, LAST>(RowSrc{row}, row, P, tw, surface, keys);
-}
-
 // The first forward pass over rows, its input packed from the two frames on
-// the fly (PackSrc); output rows to g.z. grid: P blocks, as k_fft_rows
+// the fly (PackSrc); output rows to g.z. grid and LDS as fft_row
 template <typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_fft_rows_pack(PhArgs g, const float2 *tw)
 {
     fft_row<false, false>(PackSrc<TA, TB>{g, (int)blockIdx.x}, g.z + (size_t)blockIdx.x * g.P, g.P, tw, nullptr,
-                          nullptr);
+                          nullptr, (int)blockIdx.x);
 }
 
 // The first inverse pass over rows, its input the cross power made on the
 // fly from the transposed spectrum zt (CrossSrc); output rows to rt.
-// grid: P blocks, as k_fft_rows
+// grid and LDS as fft_row
 __global__ __launch_bounds__(256) void k_fft_rows_cross(const float2 *zt, float2 *rt, int32_t P, const float2 *tw)
 {
-    fft_row<true, false>(CrossSrc{zt, (int)blockIdx.x, P}, rt + (size_t)blockIdx.x * P, P, tw, nullptr, nullptr);
+    fft_row<true, false>(CrossSrc{zt, (int)blockIdx.x, P}, rt + (size_t)blockIdx.x * P, P, tw, nullptr, nullptr,
+                         (int)blockIdx.x);
 }
 
-// out = in^T for P x P complex fields, 32 x 32 tiles through LDS.
-// grid: (ceil(P/32), ceil(P/32)), 256 threads
-__global__ __launch_bounds__(256) void k_transpose(const float2 *in, float2 *out, int32_t P)
+// Column q of m, for a row pass over m^T.
+struct ColSrc {
+    const float2 *m;
+    int q, P;
+    __device__ float2 operator()(int x) const { return m[(size_t)x * P + q]; }
+};
+
+// Row q of out = the row pass over column q of in (in^T's row q): a
+// transpose and a row pass in one. Columns go to XCDs in contiguous runs so
+// neighbouring columns share cache lines in one L2. grid and LDS as fft_row
+template <bool INV, bool LAST>
+__global__ __launch_bounds__(256) void k_fft_cols(const float2 *in, float2 *out, int32_t P, const float2 *tw,
+                                                  float *surface, unsigned long long *keys)
 {
-    __shared__ float2 t[32][33];
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-    for (int k = 0; k < 32; k += 8)
-        if (by + ty + k < P && bx + tx < P) t[ty + k][tx] = in[(size_t)(by + ty + k) * P + bx + tx];
-    __syncthreads();
-    for (int k = 0; k < 32; k += 8)
-        if (bx + ty + k < P && by + tx < P) out[(size_t)(bx + ty + k) * P + by + tx] = t[tx][ty + k];
+    const uint32_t n = gridDim.x, n8 = n & ~7u;
+    uint32_t q = blockIdx.x;
+    if (q < n8) q = (q & 7u) * (n8 >> 3) + (q >> 3);
+    fft_row<INV, LAST>(ColSrc{in, (int)q, P}, out + (size_t)q * P, P, tw, surface, keys, (int)q);
 }
 
 struct ApplyArgs {
