@@ -212,3 +212,34 @@ def test_server_config_rejected_before_any_device_work(F):
     assert per > L.roi_stream_state_bytes(2048, 2048, 1, ctypes.byref(good.params))
     assert L.roi_server_poll(None, None, 4) == 0
     assert L.roi_server_submit(None, 0, None, 64, None, None, 0) == F.ROI_EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """No fallback: with the library absent every entry raises."""
+    import subprocess
+    import sys
+    code = ("import paper_2511_14419_amd.flowroi as fl\n"
+            "fl._LIB_PATH = %r\n"
+            "fl._lib = None\n"
+            "try:\n"
+            "    fl.default_params()\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    print('no error')\n" % str(tmp_path / "libflowroi.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.startswith("raised:") and "not built" in r.stdout
+
+
+def test_product_package_never_loads_the_oracle():
+    """The oracle is test infrastructure: nothing in the package imports,
+    links or loads it (only tests, the smoke check and the benchmark's CPU
+    baseline may)."""
+    pkg = os.path.join(ROOT, "paper_2511_14419_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".h", ".hip", ".cpp", ".c")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
+                assert "flowroi_oracle" not in text and "liboracle" not in text, f
