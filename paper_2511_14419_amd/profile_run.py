@@ -19,7 +19,10 @@ heuristic).
 ``--mode`` selects the path: ``plain`` (default parameters), ``saliency``
 (the saliency rule: top 20 % of saliency, 3x3 opening and closing,
 components of at least 32 px), ``stabilize`` (phase-correlation
-stabilisation on) or ``denoise`` (denoising pre-stage on, sigma_range 60).
+stabilisation on), ``denoise`` (denoising pre-stage on, sigma_range 60) or
+``batched`` (the 16 lens streams of uneven sizes, one roi_mask_batched
+launch per step, ``--pairs`` steps after one warm-up launch that captures
+the graph).
 """
 import argparse
 
@@ -31,7 +34,7 @@ def main():
     ap.add_argument("--pairs", type=int, default=3)
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--fp16", action="store_true")
-    ap.add_argument("--mode", choices=["plain", "saliency", "stabilize", "denoise"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "saliency", "stabilize", "denoise", "batched"], default="plain")
     ap.add_argument("--strip", type=int, default=0)
     args = ap.parse_args()
 
@@ -46,6 +49,20 @@ def main():
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
+    if args.mode == "batched":
+        seqs = synth.lens_streams(16, 2)
+        prevs = [torch.from_numpy(q[0]).to(dev) for q in seqs]
+        nexts = [torch.from_numpy(q[1]).to(dev) for q in seqs]
+        flows = [torch.empty((x.shape[0], x.shape[1], 2), device=dev) for x in prevs]
+        masks = [torch.empty(x.shape, dtype=torch.uint8, device=dev) for x in prevs]
+        p = fl.default_params()
+        pairs = fl.make_pairs(prevs, nexts, flows, masks)
+        ws = fl.alloc_workspace(fl.batched_workspace_size(pairs, fl.ROI_U16, p), dev)
+        for _ in range(args.pairs + 1):
+            fl.roi_mask_batched(pairs, fl.ROI_U16, p, ws)
+        torch.cuda.synchronize()
+        print("profile_run: %d batched launches of 16 lens-stream pairs done" % (args.pairs + 1), flush=True)
+        return
     n = args.size
     seq = synth.sequence_u16(n, n, args.pairs + 1, max(1, 200 * n * n // (2048 * 2048)), 100)
     frames = [torch.from_numpy(s).to(dev) for s in seq]
